@@ -1,0 +1,86 @@
+"""The seeded input generator: SU(3) links, Haar statistics, exact
+exponential, slab consistency, and its Philox against numpy."""
+import numpy as np
+from scipy.linalg import expm
+
+import oracle as O
+from paper_1212_5221_amd import inputs as I
+from tests._su import GELL_MANN, to_c
+from tests.test_oracle_random import _numpy_philox
+
+
+def test_links_are_su3():
+    dims = (4, 4, 2, 4)
+    for U in (I.smooth(dims, 0.5, 1), I.pure_gauge(dims, 2), I.hot(dims, 3)):
+        C = to_c(U).reshape(-1, 3, 3)
+        assert np.max(np.abs(C @ C.conj().transpose(0, 2, 1) - np.eye(3))) < 1e-14
+        assert np.max(np.abs(np.linalg.det(C) - 1)) < 1e-14
+
+
+def test_exponential_matches_scipy():
+    rng = np.random.default_rng(0)
+    for eps in (0.0, 0.3, 0.7, 2.0):
+        xi = rng.normal(size=8)
+        H = eps * np.einsum("a,aij->ij", xi, GELL_MANN)
+        np.testing.assert_allclose(to_c(I.link_exponential(xi, eps)), expm(1j * H), atol=1e-14)
+
+
+def test_haar_moments():
+    dims = (16, 8, 8, 8)
+    h = to_c(I.haar_field(dims, 5))
+    tr = np.trace(h, axis1=1, axis2=2)
+    n = len(tr)
+    assert abs(tr.mean()) < 5 / np.sqrt(n)
+    assert abs(np.mean(np.abs(tr) ** 2) - 1) < 6 / np.sqrt(n)
+    # E |h_ij|^2 = 1/3 for every entry
+    np.testing.assert_allclose(np.mean(np.abs(h) ** 2, axis=0), np.full((3, 3), 1 / 3), atol=6 / np.sqrt(n))
+
+
+def test_pure_gauge_is_gauge_of_unit_links():
+    dims = (4, 2, 4, 2)
+    U = I.pure_gauge(dims, 7)
+    assert abs(O.plaquette(U, dims) - 1) < 1e-14
+    h = to_c(I.haar_field(dims, 7))
+    C = to_c(U)
+    V = len(h)
+    from tests._su import coords, site_index
+    for s in range(0, V, 7):
+        t, x, y, z = coords(dims, s)
+        for mu in range(4):
+            c = [t, x, y, z]
+            c[mu] = (c[mu] + 1) % dims[mu]
+            np.testing.assert_allclose(C[s, mu], h[s] @ h[site_index(dims, *c)].conj().T, atol=1e-14)
+
+
+def test_slabs_equal_whole():
+    dims = (6, 4, 2, 4)
+    full = I.smooth(dims, 0.5, 9)
+    vs = 32
+    part = I.smooth(dims, 0.5, 9, t0=2, nt=3)
+    np.testing.assert_array_equal(part, full[2 * vs:5 * vs])
+    last = I.smooth(dims, 0.5, 9, t0=5, nt=1)
+    np.testing.assert_array_equal(last, full[5 * vs:])
+
+
+def test_gauge_copy_keeps_invariants():
+    dims = (4, 4, 4, 2)
+    U = I.smooth(dims, 0.5, 10)
+    p = O.wilson_loop(U, dims, 1, 2)
+    F = O.measure(U, dims, "landau")[0]
+    V = U.copy()
+    I.gauge_copy(V, dims, 5100)
+    assert abs(O.wilson_loop(V, dims, 1, 2) - p) < 1e-14
+    assert abs(O.measure(V, dims, "landau")[0] - F) > 1e-3
+
+
+def test_generator_philox_matches_numpy():
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        ctr = [int(x) for x in rng.integers(0, 2 ** 63, size=4)]
+        key = [int(x) for x in rng.integers(0, 2 ** 63, size=2)]
+        np.testing.assert_array_equal(I.philox4x64_10(ctr, key), _numpy_philox(ctr, key))
+
+
+def test_smooth_eps_zero_is_pure_gauge():
+    dims = (2, 4, 2, 2)
+    np.testing.assert_allclose(I.smooth(dims, 0.0, 4), I.pure_gauge(dims, 4), atol=1e-15)
