@@ -1,0 +1,206 @@
+/*
+ * gf.h -- C ABI of libgf.so: SU(3) lattice gauge fixing on AMD Instinct
+ * MI355X (gfx950) by checkerboard overrelaxation and simulated annealing.
+ *
+ * Method: M. Schroeck and H. Vogt, "Coulomb, Landau and Maximally Abelian
+ * Gauge Fixing in Lattice QCD with Multi-GPUs", arXiv:1212.5221.
+ *   - gauge functionals F and precisions theta: Sec. 2.1;
+ *   - local updates (relaxation, overrelaxation, microcanonical, stochastic
+ *     relaxation): Sec. 2.2, App. A;
+ *   - simulated annealing with heatbath updates: Sec. 2.3;
+ *   - the even/odd sweep, Alg. 1: Sec. 2.4;
+ *   - 12-real compression and reprojection: Sec. 4.2, Sec. 4.5.
+ *
+ * Conventions
+ *   - Every function returns a status: GF_OK (0), a warning (> 0) or an error
+ *     (< 0).  No exception crosses the ABI.  gf_last_error() describes the
+ *     last non-OK status of a handle.
+ *   - A handle belongs to one host thread at a time.  All device work is
+ *     enqueued on the handle's HIP stream; host outputs are valid when the
+ *     call returns.
+ *   - The library never allocates device memory: the caller allocates one
+ *     workspace (gf_workspace_size / gf_bind_workspace) and owns it.
+ *   - Links exchanged with the caller are in the natural order (Sec. 4.2.1,
+ *     "StandardPattern"): t, x, y, z, mu, i, j, re/im with z fastest, 18
+ *     doubles per link, mu = 0 the time direction.  Boundaries are periodic.
+ */
+#ifndef GF_H
+#define GF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gf_ctx *gf_handle;
+
+/* status codes */
+#define GF_OK 0
+#define GF_NOT_CONVERGED 1 /* some instance or time-slice hit max_sweeps */
+#define GF_E_INVALID (-1)  /* bad argument (null pointer, value out of range) */
+#define GF_E_DIMS (-2)     /* lattice extent odd, < 2, or too large */
+#define GF_E_STATE (-3)    /* call not allowed in the current state */
+#define GF_E_HIP (-4)      /* a HIP runtime error; the message names it */
+#define GF_E_NOMEM (-5)    /* workspace too small or misaligned */
+#define GF_E_NONFINITE (-6) /* F or theta is not finite */
+
+/* gauges (Sec. 2.1) */
+#define GF_LANDAU 0
+#define GF_COULOMB 1
+#define GF_MAG 2
+
+/* update types (Sec. 2.2, 2.3) */
+#define GF_OR 0       /* overrelaxation g -> g^omega to first order; omega = 1 is relaxation */
+#define GF_MICRO 1    /* microcanonical step, g -> g^2 */
+#define GF_ANNEAL 2   /* the annealing schedule of gf_set_anneal */
+#define GF_SR 3       /* stochastic relaxation: g^2 with probability p, else g */
+#define GF_HEATBATH 4 /* heatbath sweeps at the fixed temperature of gf_set_temperature */
+
+/* link storage on the device (Sec. 4.2) */
+#define GF_F64_R18 0       /* double, all 18 reals */
+#define GF_F64_R12 1       /* double, first two rows; third row = (u x v)^* */
+#define GF_MIXED_F32_R12 2 /* float, first two rows; FP64 reductions and reprojection */
+
+/* gf_download flags */
+#define GF_DL_REUNITARISE 1 /* reproject every link to SU(3) in FP64 while converting */
+
+/* Create a handle on HIP device `hip_device`.  `hip_stream` is a hipStream_t
+   of that device (for example torch.cuda.current_stream().cuda_stream);
+   NULL means the default stream.  *out receives the handle. */
+int gf_create(gf_handle *out, int hip_device, void *hip_stream);
+
+/* Destroy a handle.  Frees host state only; the workspace stays the caller's. */
+void gf_destroy(gf_handle h);
+
+/* Message of the last non-OK status on `h` (or of the last failed gf_create
+   when h is NULL); valid until the next call on that handle. */
+const char *gf_last_error(gf_handle h);
+
+/* Add a lattice instance of extents dims = {Nt, Nx, Ny, Nz}.  Every extent
+   must be even and >= 2 (checkerboard with periodic boundaries); otherwise
+   GF_E_DIMS.  *inst receives the instance number (0, 1, ...).  Only before
+   gf_bind_workspace.  Instances are independent problems (Gribov copies,
+   uneven lattices) swept together with per-instance stopping. */
+int gf_add_instance(gf_handle h, const int32_t dims[4], int32_t *inst);
+
+/* Gauge for all instances (Sec. 2.1): GF_LANDAU, GF_COULOMB or GF_MAG.
+   Coulomb gauge treats every time-slice as its own problem with its own
+   stopping (Sec. 2.1.1) and applies the accumulated transformation to the
+   temporal links at the end of each gf_sweep (Sec. 5).  Only before binding. */
+int gf_set_gauge(gf_handle h, int gauge);
+
+/* Storage (GF_F64_R18, GF_F64_R12, GF_MIXED_F32_R12), reprojection interval
+   (reproject every link after every `reunit_every` sweeps; 0 = never,
+   Sec. 4.5) and, for mixed storage, the threshold below which the local
+   update is computed in FP64 instead of FP32 (the "final iterations" of a
+   run): compute in FP64 once the last measured theta of a unit is below
+   `fp64_tail_theta` (0 = never, >= 1e300 = always).  Only before binding. */
+int gf_set_precision(gf_handle h, int storage, int32_t reunit_every, double fp64_tail_theta);
+
+/* Bytes of device workspace the bound configuration needs. */
+int gf_workspace_size(gf_handle h, size_t *bytes);
+
+/* Bind the caller's device workspace: 256-byte aligned, at least
+   gf_workspace_size bytes (else GF_E_NOMEM).  After binding no instance,
+   gauge or precision can change.  The workspace holds the links in the
+   library's internal layout; its previous contents are ignored. */
+int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes);
+
+/* Copy time-slices [t0, t0+nt) of instance `inst` from `links` (natural
+   layout, nt*Nx*Ny*Nz*4*18 doubles) into the device storage, converting
+   precision and dropping the third row for 12-real storage.  on_device != 0:
+   `links` is a device pointer, else a host pointer (staged through the
+   workspace).  Enqueued on the handle's stream; returns after the copy. */
+int gf_upload(gf_handle h, int32_t inst, const double *links, int32_t t0, int32_t nt, int on_device);
+
+/* The inverse of gf_upload (the third row reconstructed in FP64 for 12-real
+   storage).  flags: GF_DL_REUNITARISE to reproject in FP64 while converting. */
+int gf_download(gf_handle h, int32_t inst, double *links, int32_t t0, int32_t nt, int on_device, int flags);
+
+/* Overrelaxation parameter omega in [1, 2) (Sec. 2.2.3); 1 = relaxation. */
+int gf_set_overrelax(gf_handle h, double omega);
+
+/* Probability p in [0, 1] of the microcanonical step in stochastic
+   relaxation (Sec. 2.2.5). */
+int gf_set_stochastic(gf_handle h, double p);
+
+/* Seed of the random streams of GF_HEATBATH, GF_SR and GF_ANNEAL sweeps
+   (Philox4x64-10 keyed by (seed, instance)); default 0. */
+int gf_set_seed(gf_handle h, uint64_t seed);
+
+/* Fixed heatbath temperature T > 0 for GF_HEATBATH sweeps (Sec. 2.3). */
+int gf_set_temperature(gf_handle h, double T);
+
+/* Annealing schedule for GF_ANNEAL (Sec. 2.3): for k = 0..nsteps-1,
+   T_k = T0 + (T1 - T0) k / (nsteps - 1); one heatbath sweep at T_k followed
+   by nmicro microcanonical sweeps.  `seed` keys the random streams
+   (Philox4x64-10 keyed by (seed, instance), counter (sweep index, site,
+   subgroup, draw)).  T0, T1 > 0, nsteps >= 1, nmicro >= 0. */
+int gf_set_anneal(gf_handle h, double T0, double T1, int32_t nsteps, int32_t nmicro, uint64_t seed);
+
+/* Run Alg. 1 with update `update`.
+   GF_OR, GF_MICRO, GF_SR, GF_HEATBATH: measure theta on the input and after
+   every `check_every` sweeps; a unit (instance; Coulomb: time-slice) stops
+   at the first check with theta < theta_tol; stop when every unit stopped
+   (GF_OK) or after max_sweeps sweeps (GF_NOT_CONVERGED).
+   GF_ANNEAL: run the schedule of gf_set_anneal (no stopping; max_sweeps,
+   theta_tol, check_every ignored).
+   sweeps_done (host, may be NULL): per instance (Landau/MAG) or per
+   instance and time-slice, instance-major (Coulomb), the sweeps each unit ran.
+   Synchronises the stream before returning. */
+int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int32_t check_every,
+             int32_t *sweeps_done);
+
+/* One half-sweep (the sites of one parity of every instance) without any
+   check: for tests of single updates.  parity: 0 even, 1 odd (Coulomb: the
+   3D parity inside each time-slice).  Uses the global sweep index as the
+   random counter and does not advance it. */
+int gf_halfsweep(gf_handle h, int update, int parity);
+
+/* F and theta of instance `inst` (Sec. 2.1) reduced in FP64 at the current
+   state; Coulomb: averages over the time-slices.  GF_E_NONFINITE if either is
+   not finite. */
+int gf_measure(gf_handle h, int32_t inst, double *F, double *theta);
+
+/* Coulomb: per time-slice F_t, theta_t (Nt values each). */
+int gf_measure_timeslices(gf_handle h, int32_t inst, double *F_t, double *theta_t);
+
+/* Mean and maximum of |1 - det U| over the links of `inst` (Sec. 4.5). */
+int gf_unitarity(gf_handle h, int32_t inst, double *mean, double *max);
+
+/* Reproject every link (and the Coulomb accumulator) to SU(3) in FP64. */
+int gf_reunitarise(gf_handle h);
+
+/* Global sweep index of instance `inst`, the random-stream counter
+   (checkpoint / resume of annealing runs). */
+int gf_get_sweep_index(gf_handle h, int32_t inst, uint64_t *index);
+int gf_set_sweep_index(gf_handle h, int32_t inst, uint64_t index);
+
+/* Kernel configuration.  lanes_per_site: lanes of a wavefront sharing one
+   site (1, 2 or 4; 0 = library default); block: threads per workgroup (64,
+   128, 256 or 512; 0 = default).  GF_E_INVALID for an unavailable variant. */
+int gf_set_launch(gf_handle h, int lanes_per_site, int block);
+
+/* Time the available launch variants of the OR half-sweep on the bound
+   configuration (each variant runs `reps` real OR sweeps, which advance the
+   fixing) and keep the fastest.  *lanes_per_site and *block (may be NULL)
+   receive the choice. */
+int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block);
+
+/* Kernel timing: while enabled, every half-sweep launch is bracketed by HIP
+   events on the handle's stream.  gf_kernel_time returns the number of
+   timed half-sweep launches and their mean duration in milliseconds since
+   timing was last enabled. */
+int gf_set_timing(gf_handle h, int enable);
+int gf_kernel_time(gf_handle h, int64_t *launches, double *mean_ms);
+
+/* HIP graph capture of the sweep loop between checks (1 = on, default). */
+int gf_set_graph(gf_handle h, int enable);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF_H */

@@ -1,0 +1,1004 @@
+// gf_api.cpp -- the C ABI of libgf (include/gf.h): handle state, workspace
+// carving, instance and unit tables, the Alg. 1 driver with per-unit
+// stopping, annealing schedules, HIP-graph capture of the sweep loop,
+// kernel timing and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gf.h"
+#include "gf_launch.hpp"
+#include "gf_shared.hpp"
+
+namespace {
+
+struct InstHost {
+    int32_t n[4];
+    int64_t V, Vh;
+    int32_t unit0, nunits;
+    int64_t links_off, g_off;
+};
+
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int key_upd = -1, key_n = -1, key_W = -1, key_tail = -1;
+    void clear() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        key_upd = key_n = key_W = key_tail = -1;
+    }
+};
+
+}  // namespace
+
+struct gf_ctx {
+    int dev = 0;
+    hipStream_t stream = nullptr;  // the caller's stream: all work is ordered on it
+    hipStream_t cur = nullptr;     // where launches go: `stream`, or `cap` while capturing a graph
+    hipStream_t cap = nullptr;     // private stream used only to capture graphs
+    std::string err;
+
+    std::vector<InstHost> inst;
+    int gauge = GF_LANDAU;
+    int storage = GF_F64_R18;
+    int reunit_every = 0;
+    double tail_theta = 0.0;
+    double omega = 1.0, p_sr = 0.5, T = 1.0;
+    double sa_T0 = 1.0, sa_T1 = 0.01;
+    int sa_steps = 0, sa_micro = 3;
+    uint64_t seed = 0;
+
+    bool bound = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+
+    // workspace layout (byte offsets)
+    size_t off_inst = 0, off_unit = 0, off_tiles = 0, off_mtiles = 0, off_partial = 0, off_res = 0;
+    size_t off_active = 0, off_fp64 = 0, off_sweeps = 0, off_sweepix = 0, off_status = 0, off_stage = 0;
+    size_t stage_bytes = 0, need_bytes = 0;
+    int nunits = 0, nmtiles = 0;
+    int64_t max_tiles = 0;
+    std::vector<gfs::UnitDev> units;
+
+    // launch configuration
+    int W = 1;
+    int ntiles = 0;  // sweep tiles for the current W
+
+    // host readback (pinned)
+    int32_t *hstat = nullptr;
+    double *hres = nullptr;
+
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    double t_sum_ms = 0.0;
+    int64_t t_count = 0;
+
+    bool use_graph = true;
+    GraphCache graph;
+};
+
+namespace {
+
+std::string g_create_error;
+
+int fail(gf_ctx *h, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h)
+        h->err = buf;
+    else
+        g_create_error = buf;
+    return code;
+}
+
+#define HIPCHK(h, call)                                                                                   \
+    do {                                                                                                  \
+        hipError_t e_ = (call);                                                                           \
+        if (e_ != hipSuccess) return fail((h), GF_E_HIP, "%s: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                                          __FILE__, __LINE__);                                            \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int nchunks(int storage) {
+    switch (storage) {
+    case GF_F64_R18:
+        return 9;
+    case GF_F64_R12:
+        return 6;
+    default:
+        return 3;
+    }
+}
+
+int st_code(int storage) {
+    switch (storage) {
+    case GF_F64_R18:
+        return gfs::ST_F64R18;
+    case GF_F64_R12:
+        return gfs::ST_F64R12;
+    default:
+        return gfs::ST_F32R12;
+    }
+}
+
+int ndir(const gf_ctx *h) { return h->gauge == GF_COULOMB ? 3 : 4; }
+
+int upd_code(int update) {
+    switch (update) {
+    case GF_OR:
+        return gfs::UPD_OR;
+    case GF_MICRO:
+        return gfs::UPD_MICRO;
+    case GF_SR:
+        return gfs::UPD_SR;
+    case GF_HEATBATH:
+        return gfs::UPD_HEATBATH;
+    default:
+        return -1;
+    }
+}
+
+int default_W(const gf_ctx *h) {
+    (void)h;
+    return 1;
+}
+
+template <typename T>
+T *wsp(gf_ctx *h, size_t off) {
+    return reinterpret_cast<T *>(h->ws + off);
+}
+
+// compute the layout; with ws == nullptr only the size
+void plan_layout(gf_ctx *h) {
+    size_t off = 0;
+    const int nch = nchunks(h->storage);
+    int unit = 0;
+    for (auto &I : h->inst) {
+        I.links_off = (int64_t)off;
+        off += align256((size_t)8 * nch * I.Vh * 16);
+        I.unit0 = unit;
+        I.nunits = (h->gauge == GF_COULOMB) ? I.n[0] : 1;
+        unit += I.nunits;
+        if (h->gauge == GF_COULOMB) {
+            I.g_off = (int64_t)off;
+            off += align256((size_t)2 * nch * I.Vh * 16);
+        } else {
+            I.g_off = -1;
+        }
+    }
+    h->nunits = unit;
+    h->units.clear();
+    int mt = 0;
+    int64_t tiles_min = 0;
+    for (size_t i = 0; i < h->inst.size(); ++i) {
+        const InstHost &I = h->inst[i];
+        for (int k = 0; k < I.nunits; ++k) {
+            gfs::UnitDev u;
+            u.inst = (int32_t)i;
+            if (h->gauge == GF_COULOMB) {
+                const int32_t hs = (int32_t)(I.Vh / I.n[0]);
+                u.t = k;
+                u.h0 = k * hs;
+                u.n = hs;
+            } else {
+                u.t = -1;
+                u.h0 = 0;
+                u.n = (int32_t)I.Vh;
+            }
+            const int per = (u.n + 255) / 256;
+            u.mtile0 = mt;
+            mt += 2 * per;
+            u.mtile1 = mt;
+            tiles_min += (u.n + 63) / 64;
+            h->units.push_back(u);
+        }
+    }
+    h->nmtiles = mt;
+    h->max_tiles = tiles_min;
+    h->off_inst = off;
+    off += align256(sizeof(gfs::InstDev) * h->inst.size());
+    h->off_unit = off;
+    off += align256(sizeof(gfs::UnitDev) * h->nunits);
+    h->off_tiles = off;
+    off += align256(sizeof(gfs::Tile) * (size_t)h->max_tiles);
+    h->off_mtiles = off;
+    off += align256(sizeof(gfs::MTile) * (size_t)h->nmtiles);
+    h->off_partial = off;
+    off += align256(sizeof(double) * 4 * (size_t)h->nmtiles);
+    h->off_res = off;
+    off += align256(sizeof(double) * 4 * (size_t)h->nunits);
+    h->off_active = off;
+    off += align256(sizeof(int32_t) * h->nunits);
+    h->off_fp64 = off;
+    off += align256(sizeof(int32_t) * h->nunits);
+    h->off_sweeps = off;
+    off += align256(sizeof(int32_t) * h->nunits);
+    h->off_sweepix = off;
+    off += align256(sizeof(uint64_t) * h->inst.size());
+    h->off_status = off;
+    off += 256;
+    // staging for host uploads/downloads: up to 32 MiB, at least one site
+    int64_t maxV = 0;
+    for (auto &I : h->inst) maxV = std::max(maxV, I.V);
+    h->stage_bytes = align256(std::min<size_t>((size_t)32 << 20, (size_t)maxV * 576));
+    h->off_stage = off;
+    off += h->stage_bytes;
+    h->need_bytes = off;
+}
+
+gfs::InstDev inst_dev(const InstHost &I) {
+    gfs::InstDev d;
+    for (int k = 0; k < 4; ++k) d.n[k] = I.n[k];
+    d.Vh = (int32_t)I.Vh;
+    d.unit0 = I.unit0;
+    d.nunits = I.nunits;
+    d.pad = 0;
+    d.links_off = I.links_off;
+    d.g_off = I.g_off;
+    return d;
+}
+
+int build_tiles(gf_ctx *h, int W) {
+    const int spb = gfl::SWEEP_THREADS / W;
+    std::vector<gfs::Tile> t;
+    for (int u = 0; u < h->nunits; ++u)
+        for (int32_t j = 0; j < h->units[u].n; j += spb) t.push_back({u, j});
+    if ((int64_t)t.size() > h->max_tiles) return fail(h, GF_E_INVALID, "tile table overflow");
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_tiles, t.data(), sizeof(gfs::Tile) * t.size(), hipMemcpyHostToDevice,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->ntiles = (int)t.size();
+    h->W = W;
+    h->graph.clear();
+    return GF_OK;
+}
+
+int check_bound(gf_ctx *h) {
+    if (!h) return GF_E_INVALID;
+    if (!h->bound) return fail(h, GF_E_STATE, "no workspace bound (call gf_bind_workspace first)");
+    return GF_OK;
+}
+
+int check_unbound(gf_ctx *h) {
+    if (!h) return GF_E_INVALID;
+    if (h->bound) return fail(h, GF_E_STATE, "configuration is fixed once a workspace is bound");
+    return GF_OK;
+}
+
+gfs::SweepArgs sweep_args(gf_ctx *h, int parity, int fp64_select, double T) {
+    gfs::SweepArgs a;
+    a.ws = h->ws;
+    a.inst = wsp<gfs::InstDev>(h, h->off_inst);
+    a.unit = wsp<gfs::UnitDev>(h, h->off_unit);
+    a.tiles = wsp<gfs::Tile>(h, h->off_tiles);
+    a.active = wsp<int32_t>(h, h->off_active);
+    a.fp64 = wsp<int32_t>(h, h->off_fp64);
+    a.sweep_ix = wsp<uint64_t>(h, h->off_sweepix);
+    a.parity = parity;
+    a.fp64_select = fp64_select;
+    a.omega = h->omega;
+    a.T = T;
+    a.p_sr = h->p_sr;
+    a.seed = h->seed;
+    return a;
+}
+
+hipEvent_t take_event(gf_ctx *h) {
+    if (!h->ev_pool.empty()) {
+        hipEvent_t e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int drain_timing(gf_ctx *h) {
+    if (h->ev_pending.empty()) return GF_OK;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (auto &p : h->ev_pending) {
+        float ms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&ms, p.first, p.second));
+        h->t_sum_ms += ms;
+        h->t_count += 1;
+        h->ev_pool.push_back(p.first);
+        h->ev_pool.push_back(p.second);
+    }
+    h->ev_pending.clear();
+    return GF_OK;
+}
+
+// one half-sweep of update `upd` (gfs code) at temperature T on all active units
+int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing) {
+    const int st = st_code(h->storage);
+    const bool mixed = (h->storage == GF_MIXED_F32_R12);
+    const bool hb = (upd == gfs::UPD_HEATBATH || upd == gfs::UPD_SR);
+    // compute precision: FP64 storage -> double; mixed -> float (+ double tail)
+    struct L {
+        int ctd, sel;
+    } launches[2];
+    int nl = 0;
+    if (!mixed || hb) {
+        launches[nl++] = {1, -1};
+    } else if (h->tail_theta > 0.0) {
+        launches[nl++] = {0, 0};
+        launches[nl++] = {1, 1};
+    } else {
+        launches[nl++] = {0, -1};
+    }
+    for (int k = 0; k < nl; ++k) {
+        gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, st, launches[k].ctd, h->W);
+        if (!fn) return fail(h, GF_E_INVALID, "no kernel variant for gauge %d update %d storage %d W %d", h->gauge, upd,
+                             h->storage, h->W);
+        gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T);
+        const bool tm = h->timing && !capturing;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (tm) {
+            e0 = take_event(h);
+            e1 = take_event(h);
+            if (!e0 || !e1) return fail(h, GF_E_HIP, "hipEventCreate failed");
+            HIPCHK(h, hipEventRecord(e0, h->cur));
+        }
+        fn<<<dim3((unsigned)h->ntiles), dim3(gfl::SWEEP_THREADS), 0, h->cur>>>(a);
+        HIPCHK(h, hipGetLastError());
+        if (tm) {
+            HIPCHK(h, hipEventRecord(e1, h->cur));
+            h->ev_pending.push_back({e0, e1});
+            if (h->ev_pending.size() > 4096) {
+                int rc = drain_timing(h);
+                if (rc) return rc;
+            }
+        }
+    }
+    return GF_OK;
+}
+
+int launch_reunit_all(gf_ctx *h) {
+    const int st = st_code(h->storage);
+    for (auto &I : h->inst) {
+        HIPCHK(h, gfl::reunit(st, h->ws, I.links_off, 8, (int32_t)I.Vh, h->cur));
+        if (I.g_off >= 0) HIPCHK(h, gfl::reunit(st, h->ws, I.g_off, 2, (int32_t)I.Vh, h->cur));
+    }
+    return GF_OK;
+}
+
+// one full sweep (both parities) + bookkeeping [+ reprojection]
+int launch_sweep(gf_ctx *h, int upd, double T, bool reunit_now, bool capturing) {
+    for (int p = 0; p < 2; ++p) {
+        int rc = launch_half(h, upd, p, T, capturing);
+        if (rc) return rc;
+    }
+    HIPCHK(h, gfl::count_sweep((int)h->inst.size(), wsp<gfs::InstDev>(h, h->off_inst), wsp<int32_t>(h, h->off_active),
+                               wsp<int32_t>(h, h->off_sweeps), wsp<uint64_t>(h, h->off_sweepix), h->cur));
+    if (reunit_now) return launch_reunit_all(h);
+    return GF_OK;
+}
+
+int launch_measure(gf_ctx *h, int with_unitarity) {
+    gfs::MeasureArgs a;
+    a.ws = h->ws;
+    a.inst = wsp<gfs::InstDev>(h, h->off_inst);
+    a.unit = wsp<gfs::UnitDev>(h, h->off_unit);
+    a.tiles = wsp<gfs::MTile>(h, h->off_mtiles);
+    a.partial = wsp<double>(h, h->off_partial);
+    a.with_unitarity = with_unitarity;
+    HIPCHK(h, gfl::measure(h->gauge, st_code(h->storage), (unsigned)h->nmtiles, h->cur, a));
+    HIPCHK(h, gfl::finalize(h->nunits, wsp<gfs::UnitDev>(h, h->off_unit), wsp<double>(h, h->off_partial), ndir(h),
+                            wsp<double>(h, h->off_res), h->cur));
+    return GF_OK;
+}
+
+int launch_decide(gf_ctx *h, double tol) {
+    const double tail = (h->storage == GF_MIXED_F32_R12) ? h->tail_theta : 0.0;
+    HIPCHK(h, gfl::decide(h->nunits, wsp<double>(h, h->off_res), wsp<int32_t>(h, h->off_active),
+                          wsp<int32_t>(h, h->off_fp64), tol, tail, wsp<int32_t>(h, h->off_status), h->cur));
+    return GF_OK;
+}
+
+int read_status(gf_ctx *h) {
+    HIPCHK(h, hipMemcpyAsync(h->hstat, h->ws + h->off_status, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return GF_OK;
+}
+
+int coulomb_finish(gf_ctx *h) {
+    if (h->gauge != GF_COULOMB) return GF_OK;
+    const int st = st_code(h->storage);
+    for (auto &I : h->inst) {
+        const gfs::InstDev d = inst_dev(I);
+        HIPCHK(h, gfl::coulomb_fix(st, h->ws, d, h->cur));
+        HIPCHK(h, gfl::set_identity(st, h->ws, I.g_off, (int32_t)I.Vh, h->cur));
+    }
+    return GF_OK;
+}
+
+// run `n` sweeps starting at sweep count k0 (of this gf_sweep call)
+int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
+    const int R = h->reunit_every;
+    // a graph replays a chunk of n sweeps; reprojection points must not depend
+    // on k0, so graphs are used only when no reprojection falls inside or
+    // when R divides the chunk boundary pattern identically
+    const bool graph_ok = h->use_graph && !h->timing && chunk_is_full && (R == 0 || (n % R == 0 && k0 % R == 0));
+    if (!graph_ok) {
+        for (int i = 0; i < n; ++i) {
+            const bool rn = (R > 0) && ((k0 + i + 1) % R == 0);
+            int rc = launch_sweep(h, upd, h->T, rn, false);
+            if (rc) return rc;
+        }
+        return GF_OK;
+    }
+    const int tailkey = (h->storage == GF_MIXED_F32_R12 && h->tail_theta > 0.0) ? 1 : 0;
+    GraphCache &g = h->graph;
+    if (!(g.exec && g.key_upd == upd && g.key_n == n && g.key_W == h->W && g.key_tail == tailkey)) {
+        g.clear();
+        if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+        h->cur = h->cap;
+        int rc = GF_OK;
+        for (int i = 0; i < n && rc == GF_OK; ++i) {
+            const bool rn = (R > 0) && ((i + 1) % R == 0);
+            rc = launch_sweep(h, upd, h->T, rn, true);
+        }
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(h->cap, &gr);
+        h->cur = h->stream;
+        if (rc) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(h, GF_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        g.graph = gr;
+        HIPCHK(h, hipGraphInstantiate(&g.exec, gr, nullptr, nullptr, 0));
+        g.key_upd = upd;
+        g.key_n = n;
+        g.key_W = h->W;
+        g.key_tail = tailkey;
+    }
+    HIPCHK(h, hipGraphLaunch(g.exec, h->stream));
+    return GF_OK;
+}
+
+int fetch_sweeps_done(gf_ctx *h, int32_t *sweeps_done) {
+    if (!sweeps_done) return GF_OK;
+    HIPCHK(h, hipMemcpyAsync(sweeps_done, h->ws + h->off_sweeps, sizeof(int32_t) * h->nunits, hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return GF_OK;
+}
+
+int check_inst(gf_ctx *h, int32_t inst) {
+    if (inst < 0 || inst >= (int32_t)h->inst.size()) return fail(h, GF_E_INVALID, "no instance %d", inst);
+    return GF_OK;
+}
+
+}  // namespace
+
+namespace gfl {
+sweep_fn sweep_kernel(int gauge, int upd, int st, int ct_double, int W) {
+    if (gauge == gfs::LANDAU) return sweep_kernel_landau(upd, st, ct_double, W);
+    if (gauge == gfs::COULOMB) return sweep_kernel_coulomb(upd, st, ct_double, W);
+    return sweep_kernel_mag(upd, st, ct_double, W);
+}
+}  // namespace gfl
+
+// ======================================================================== ABI
+extern "C" {
+
+int gf_create(gf_handle *out, int hip_device, void *hip_stream) {
+    if (!out) return fail(nullptr, GF_E_INVALID, "gf_create: out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return fail(nullptr, GF_E_HIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (hip_device < 0 || hip_device >= ndev) return fail(nullptr, GF_E_INVALID, "no HIP device %d", hip_device);
+    e = hipSetDevice(hip_device);
+    if (e != hipSuccess) return fail(nullptr, GF_E_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+    gf_ctx *h = new gf_ctx();
+    h->dev = hip_device;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    h->cur = h->stream;
+    e = hipHostMalloc(reinterpret_cast<void **>(&h->hstat), 64, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(nullptr, GF_E_HIP, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return GF_OK;
+}
+
+void gf_destroy(gf_handle h) {
+    if (!h) return;
+    (void)hipSetDevice(h->dev);
+    if (!h->ev_pending.empty()) (void)hipStreamSynchronize(h->stream);
+    h->graph.clear();
+    for (auto &p : h->ev_pending) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->hstat) (void)hipHostFree(h->hstat);
+    if (h->hres) (void)hipHostFree(h->hres);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    delete h;
+}
+
+const char *gf_last_error(gf_handle h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+int gf_add_instance(gf_handle h, const int32_t dims[4], int32_t *inst) {
+    int rc = check_unbound(h);
+    if (rc) return rc;
+    if (!dims) return fail(h, GF_E_INVALID, "dims is NULL");
+    int64_t V = 1;
+    for (int k = 0; k < 4; ++k) {
+        if (dims[k] < 2 || (dims[k] & 1))
+            return fail(h, GF_E_DIMS, "extent %d of dimension %d is not even and >= 2", dims[k], k);
+        V *= dims[k];
+    }
+    if (V / 2 >= ((int64_t)1 << 31)) return fail(h, GF_E_DIMS, "lattice too large (%lld sites)", (long long)V);
+    InstHost I;
+    for (int k = 0; k < 4; ++k) I.n[k] = dims[k];
+    I.V = V;
+    I.Vh = V / 2;
+    I.unit0 = I.nunits = 0;
+    I.links_off = I.g_off = 0;
+    h->inst.push_back(I);
+    if (inst) *inst = (int32_t)h->inst.size() - 1;
+    return GF_OK;
+}
+
+int gf_set_gauge(gf_handle h, int gauge) {
+    int rc = check_unbound(h);
+    if (rc) return rc;
+    if (gauge != GF_LANDAU && gauge != GF_COULOMB && gauge != GF_MAG) return fail(h, GF_E_INVALID, "bad gauge %d", gauge);
+    h->gauge = gauge;
+    return GF_OK;
+}
+
+int gf_set_precision(gf_handle h, int storage, int32_t reunit_every, double fp64_tail_theta) {
+    int rc = check_unbound(h);
+    if (rc) return rc;
+    if (storage != GF_F64_R18 && storage != GF_F64_R12 && storage != GF_MIXED_F32_R12)
+        return fail(h, GF_E_INVALID, "bad storage %d", storage);
+    if (reunit_every < 0) return fail(h, GF_E_INVALID, "reunit_every < 0");
+    if (!(fp64_tail_theta >= 0.0)) return fail(h, GF_E_INVALID, "fp64_tail_theta must be >= 0");
+    h->storage = storage;
+    h->reunit_every = reunit_every;
+    h->tail_theta = fp64_tail_theta;
+    return GF_OK;
+}
+
+int gf_workspace_size(gf_handle h, size_t *bytes) {
+    if (!h || !bytes) return fail(h, GF_E_INVALID, "NULL argument");
+    if (h->inst.empty()) return fail(h, GF_E_STATE, "no instance added");
+    plan_layout(h);
+    *bytes = h->need_bytes;
+    return GF_OK;
+}
+
+int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes) {
+    int rc = check_unbound(h);
+    if (rc) return rc;
+    if (h->inst.empty()) return fail(h, GF_E_STATE, "no instance added");
+    if (!dev_ptr) return fail(h, GF_E_INVALID, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) & 255) return fail(h, GF_E_NOMEM, "workspace not 256-byte aligned");
+    plan_layout(h);
+    if (bytes < h->need_bytes)
+        return fail(h, GF_E_NOMEM, "workspace of %zu bytes, %zu needed", bytes, h->need_bytes);
+    HIPCHK(h, hipSetDevice(h->dev));
+    h->ws = reinterpret_cast<char *>(dev_ptr);
+    h->ws_bytes = bytes;
+    std::vector<gfs::InstDev> idv;
+    for (auto &I : h->inst) idv.push_back(inst_dev(I));
+    std::vector<gfs::MTile> mt;
+    for (int u = 0; u < h->nunits; ++u) {
+        const gfs::UnitDev &U = h->units[u];
+        for (int p = 0; p < 2; ++p)
+            for (int32_t j = 0; j < U.n; j += 256) mt.push_back({u, p, j, 0});
+    }
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_inst, idv.data(), sizeof(gfs::InstDev) * idv.size(), hipMemcpyHostToDevice,
+                             h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_unit, h->units.data(), sizeof(gfs::UnitDev) * h->units.size(),
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_mtiles, mt.data(), sizeof(gfs::MTile) * mt.size(), hipMemcpyHostToDevice,
+                             h->stream));
+    std::vector<uint64_t> zero(h->inst.size(), 0);
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_sweepix, zero.data(), sizeof(uint64_t) * zero.size(), hipMemcpyHostToDevice,
+                             h->stream));
+    HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_active), 1, h->nunits, h->stream));
+    // FP64 tail flags: before any measurement theta is unknown; a threshold of
+    // 1e300 or more means "always FP64"
+    HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_fp64), h->tail_theta >= 1e300 ? 1 : 0, h->nunits, h->stream));
+    HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_sweeps), 0, h->nunits, h->stream));
+    const int st = st_code(h->storage);
+    for (auto &I : h->inst)
+        if (I.g_off >= 0) HIPCHK(h, gfl::set_identity(st, h->ws, I.g_off, (int32_t)I.Vh, h->stream));
+    if (h->hres) (void)hipHostFree(h->hres);
+    HIPCHK(h, hipHostMalloc(reinterpret_cast<void **>(&h->hres), sizeof(double) * 4 * h->nunits, hipHostMallocDefault));
+    h->bound = true;
+    rc = build_tiles(h, default_W(h));
+    if (rc) {
+        h->bound = false;
+        return rc;
+    }
+    return GF_OK;
+}
+
+static int transfer(gf_handle h, int32_t inst, double *links, int32_t t0, int32_t nt, int on_device, int dir,
+                    int flags) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    rc = check_inst(h, inst);
+    if (rc) return rc;
+    if (!links) return fail(h, GF_E_INVALID, "links is NULL");
+    const InstHost &I = h->inst[inst];
+    if (t0 < 0 || nt < 0 || t0 + nt > I.n[0]) return fail(h, GF_E_INVALID, "time slab [%d, %d) out of range", t0, t0 + nt);
+    HIPCHK(h, hipSetDevice(h->dev));
+    const int64_t Vs = I.V / I.n[0];
+    const int64_t s0 = (int64_t)t0 * Vs, ns = (int64_t)nt * Vs;
+    const gfs::InstDev d = inst_dev(I);
+    const int st = st_code(h->storage);
+    const int reun = (flags & GF_DL_REUNITARISE) ? 1 : 0;
+    if (on_device) {
+        if (dir == 0)
+            HIPCHK(h, gfl::convert_in(st, h->ws, d, links, s0, ns, h->stream));
+        else
+            HIPCHK(h, gfl::convert_out(st, h->ws, d, links, s0, ns, reun, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        return GF_OK;
+    }
+    const int64_t per = std::max<int64_t>(1, (int64_t)(h->stage_bytes / 576));
+    double *stage = wsp<double>(h, h->off_stage);
+    for (int64_t s = 0; s < ns; s += per) {
+        const int64_t c = std::min(per, ns - s);
+        if (dir == 0) {
+            HIPCHK(h, hipMemcpyAsync(stage, links + s * 72, (size_t)c * 576, hipMemcpyHostToDevice, h->stream));
+            HIPCHK(h, gfl::convert_in(st, h->ws, d, stage, s0 + s, c, h->stream));
+        } else {
+            HIPCHK(h, gfl::convert_out(st, h->ws, d, stage, s0 + s, c, reun, h->stream));
+            HIPCHK(h, hipMemcpyAsync(links + s * 72, stage, (size_t)c * 576, hipMemcpyDeviceToHost, h->stream));
+        }
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    return GF_OK;
+}
+
+int gf_upload(gf_handle h, int32_t inst, const double *links, int32_t t0, int32_t nt, int on_device) {
+    return transfer(h, inst, const_cast<double *>(links), t0, nt, on_device, 0, 0);
+}
+
+int gf_download(gf_handle h, int32_t inst, double *links, int32_t t0, int32_t nt, int on_device, int flags) {
+    return transfer(h, inst, links, t0, nt, on_device, 1, flags);
+}
+
+int gf_set_overrelax(gf_handle h, double omega) {
+    if (!h) return GF_E_INVALID;
+    if (!(omega >= 1.0 && omega < 2.0)) return fail(h, GF_E_INVALID, "omega %g not in [1, 2)", omega);
+    h->omega = omega;
+    h->graph.clear();
+    return GF_OK;
+}
+
+int gf_set_stochastic(gf_handle h, double p) {
+    if (!h) return GF_E_INVALID;
+    if (!(p >= 0.0 && p <= 1.0)) return fail(h, GF_E_INVALID, "probability %g not in [0, 1]", p);
+    h->p_sr = p;
+    h->graph.clear();
+    return GF_OK;
+}
+
+int gf_set_seed(gf_handle h, uint64_t seed) {
+    if (!h) return GF_E_INVALID;
+    h->seed = seed;
+    h->graph.clear();
+    return GF_OK;
+}
+
+int gf_set_temperature(gf_handle h, double T) {
+    if (!h) return GF_E_INVALID;
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(h, GF_E_INVALID, "temperature %g must be > 0", T);
+    h->T = T;
+    h->graph.clear();
+    return GF_OK;
+}
+
+int gf_set_anneal(gf_handle h, double T0, double T1, int32_t nsteps, int32_t nmicro, uint64_t seed) {
+    if (!h) return GF_E_INVALID;
+    if (!(T0 > 0.0) || !(T1 > 0.0) || !std::isfinite(T0) || !std::isfinite(T1))
+        return fail(h, GF_E_INVALID, "temperatures must be > 0");
+    if (nsteps < 1 || nmicro < 0) return fail(h, GF_E_INVALID, "nsteps >= 1 and nmicro >= 0 required");
+    h->sa_T0 = T0;
+    h->sa_T1 = T1;
+    h->sa_steps = nsteps;
+    h->sa_micro = nmicro;
+    h->seed = seed;
+    h->graph.clear();
+    return GF_OK;
+}
+
+int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int32_t check_every, int32_t *sweeps_done) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    HIPCHK(h, hipSetDevice(h->dev));
+    HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_sweeps), 0, h->nunits, h->stream));
+    HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_active), 1, h->nunits, h->stream));
+    if (update == GF_ANNEAL) {
+        if (h->sa_steps < 1) return fail(h, GF_E_STATE, "no annealing schedule (gf_set_anneal)");
+        for (int k = 0; k < h->sa_steps; ++k) {
+            const double T =
+                (h->sa_steps > 1) ? h->sa_T0 + (h->sa_T1 - h->sa_T0) * (double)k / (double)(h->sa_steps - 1) : h->sa_T0;
+            rc = launch_sweep(h, gfs::UPD_HEATBATH, T, false, false);
+            if (rc) return rc;
+            for (int m = 0; m < h->sa_micro; ++m) {
+                rc = launch_sweep(h, gfs::UPD_MICRO, T, false, false);
+                if (rc) return rc;
+            }
+        }
+        rc = coulomb_finish(h);
+        if (rc) return rc;
+        rc = drain_timing(h);
+        if (rc) return rc;
+        rc = fetch_sweeps_done(h, sweeps_done);
+        if (rc) return rc;
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        return GF_OK;
+    }
+    const int upd = upd_code(update);
+    if (upd < 0) return fail(h, GF_E_INVALID, "bad update type %d", update);
+    if (max_sweeps < 0) return fail(h, GF_E_INVALID, "max_sweeps < 0");
+    if (check_every < 1) check_every = 1;
+    int status = GF_OK;
+    int k = 0;
+    for (;;) {
+        if (k % check_every == 0) {
+            rc = launch_measure(h, 0);
+            if (rc) return rc;
+            rc = launch_decide(h, theta_tol);
+            if (rc) return rc;
+            rc = read_status(h);
+            if (rc) return rc;
+            if (h->hstat[1] != 0) {
+                (void)fetch_sweeps_done(h, sweeps_done);
+                return fail(h, GF_E_NONFINITE, "F or theta not finite in %d unit(s) after %d sweeps", h->hstat[1], k);
+            }
+            if (h->hstat[0] == 0) break;
+        }
+        if (k >= max_sweeps) {
+            status = GF_NOT_CONVERGED;
+            break;
+        }
+        const int n = std::min(check_every - k % check_every, max_sweeps - k);
+        rc = run_sweeps(h, upd, n, k, n == check_every);
+        if (rc) return rc;
+        k += n;
+    }
+    rc = coulomb_finish(h);
+    if (rc) return rc;
+    rc = drain_timing(h);
+    if (rc) return rc;
+    rc = fetch_sweeps_done(h, sweeps_done);
+    if (rc) return rc;
+    if (status == GF_NOT_CONVERGED) (void)fail(h, GF_NOT_CONVERGED, "not converged after %d sweeps", max_sweeps);
+    return status;
+}
+
+int gf_halfsweep(gf_handle h, int update, int parity) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    const int upd = upd_code(update);
+    if (upd < 0) return fail(h, GF_E_INVALID, "bad update type %d", update);
+    if (parity != 0 && parity != 1) return fail(h, GF_E_INVALID, "parity must be 0 or 1");
+    HIPCHK(h, hipSetDevice(h->dev));
+    HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_active), 1, h->nunits, h->stream));
+    rc = launch_half(h, upd, parity, h->T, false);
+    if (rc) return rc;
+    rc = drain_timing(h);
+    if (rc) return rc;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return GF_OK;
+}
+
+static int measure_units(gf_handle h, int with_unitarity) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    HIPCHK(h, hipSetDevice(h->dev));
+    rc = launch_measure(h, with_unitarity);
+    if (rc) return rc;
+    HIPCHK(h, hipMemcpyAsync(h->hres, h->ws + h->off_res, sizeof(double) * 4 * h->nunits, hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return GF_OK;
+}
+
+int gf_measure(gf_handle h, int32_t inst, double *F, double *theta) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    rc = check_inst(h, inst);
+    if (rc) return rc;
+    rc = measure_units(h, 0);
+    if (rc) return rc;
+    const InstHost &I = h->inst[inst];
+    double f = 0.0, t = 0.0;
+    for (int u = I.unit0; u < I.unit0 + I.nunits; ++u) {
+        f += h->hres[4 * u];
+        t += h->hres[4 * u + 1];
+    }
+    f /= I.nunits;
+    t /= I.nunits;
+    if (F) *F = f;
+    if (theta) *theta = t;
+    if (!std::isfinite(f) || !std::isfinite(t)) return fail(h, GF_E_NONFINITE, "F or theta not finite");
+    return GF_OK;
+}
+
+int gf_measure_timeslices(gf_handle h, int32_t inst, double *F_t, double *theta_t) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    rc = check_inst(h, inst);
+    if (rc) return rc;
+    if (h->gauge != GF_COULOMB) return fail(h, GF_E_STATE, "per time-slice values need Coulomb gauge");
+    rc = measure_units(h, 0);
+    if (rc) return rc;
+    const InstHost &I = h->inst[inst];
+    bool fin = true;
+    for (int k = 0; k < I.nunits; ++k) {
+        const double f = h->hres[4 * (I.unit0 + k)], t = h->hres[4 * (I.unit0 + k) + 1];
+        if (F_t) F_t[k] = f;
+        if (theta_t) theta_t[k] = t;
+        fin = fin && std::isfinite(f) && std::isfinite(t);
+    }
+    if (!fin) return fail(h, GF_E_NONFINITE, "F or theta not finite");
+    return GF_OK;
+}
+
+int gf_unitarity(gf_handle h, int32_t inst, double *mean, double *maxv) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    rc = check_inst(h, inst);
+    if (rc) return rc;
+    rc = measure_units(h, 1);
+    if (rc) return rc;
+    const InstHost &I = h->inst[inst];
+    double s = 0.0, m = 0.0;
+    for (int u = I.unit0; u < I.unit0 + I.nunits; ++u) {
+        s += h->hres[4 * u + 2];
+        m = std::max(m, h->hres[4 * u + 3]);
+    }
+    if (mean) *mean = s / I.nunits;
+    if (maxv) *maxv = m;
+    return GF_OK;
+}
+
+int gf_reunitarise(gf_handle h) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    HIPCHK(h, hipSetDevice(h->dev));
+    rc = launch_reunit_all(h);
+    if (rc) return rc;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return GF_OK;
+}
+
+int gf_get_sweep_index(gf_handle h, int32_t inst, uint64_t *index) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    rc = check_inst(h, inst);
+    if (rc) return rc;
+    if (!index) return fail(h, GF_E_INVALID, "index is NULL");
+    HIPCHK(h, hipMemcpyAsync(index, h->ws + h->off_sweepix + sizeof(uint64_t) * inst, sizeof(uint64_t),
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return GF_OK;
+}
+
+int gf_set_sweep_index(gf_handle h, int32_t inst, uint64_t index) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    rc = check_inst(h, inst);
+    if (rc) return rc;
+    uint64_t v = index;
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_sweepix + sizeof(uint64_t) * inst, &v, sizeof(uint64_t),
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return GF_OK;
+}
+
+int gf_set_launch(gf_handle h, int lanes_per_site, int block) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    const int W = lanes_per_site == 0 ? default_W(h) : lanes_per_site;
+    if (block != 0 && block != gfl::SWEEP_THREADS) return fail(h, GF_E_INVALID, "block %d not available", block);
+    const int st = st_code(h->storage);
+    if (!gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, h->storage == GF_MIXED_F32_R12 ? 0 : 1, W))
+        return fail(h, GF_E_INVALID, "no variant with %d wavefronts per site group", W);
+    return build_tiles(h, W);
+}
+
+int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (reps < 1) reps = 1;
+    const int st = st_code(h->storage);
+    const int ctd = h->storage == GF_MIXED_F32_R12 ? 0 : 1;
+    const bool was_timing = h->timing;
+    const double save_sum = h->t_sum_ms;
+    const int64_t save_cnt = h->t_count;
+    HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_active), 1, h->nunits, h->stream));
+    int bestW = h->W;
+    double best = 1e300;
+    for (int W = 1; W <= 8; W *= 2) {
+        if (!gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, ctd, W)) continue;
+        rc = build_tiles(h, W);
+        if (rc) return rc;
+        // warm-up sweep, then timed sweeps
+        rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false);
+        if (rc) return rc;
+        rc = drain_timing(h);
+        if (rc) return rc;
+        h->timing = true;
+        h->t_sum_ms = 0.0;
+        h->t_count = 0;
+        for (int r = 0; r < reps; ++r) {
+            rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false);
+            if (rc) return rc;
+        }
+        rc = drain_timing(h);
+        if (rc) return rc;
+        h->timing = was_timing;
+        const double ms = h->t_count ? h->t_sum_ms / h->t_count : 1e300;
+        if (ms < best) {
+            best = ms;
+            bestW = W;
+        }
+    }
+    h->t_sum_ms = save_sum;
+    h->t_count = save_cnt;
+    rc = build_tiles(h, bestW);
+    if (rc) return rc;
+    if (lanes_per_site) *lanes_per_site = bestW;
+    if (block) *block = gfl::SWEEP_THREADS;
+    return GF_OK;
+}
+
+int gf_set_timing(gf_handle h, int enable) {
+    if (!h) return GF_E_INVALID;
+    int rc = drain_timing(h);
+    if (rc) return rc;
+    h->timing = enable != 0;
+    h->t_sum_ms = 0.0;
+    h->t_count = 0;
+    return GF_OK;
+}
+
+int gf_kernel_time(gf_handle h, int64_t *launches, double *mean_ms) {
+    if (!h) return GF_E_INVALID;
+    int rc = drain_timing(h);
+    if (rc) return rc;
+    if (launches) *launches = h->t_count;
+    if (mean_ms) *mean_ms = h->t_count ? h->t_sum_ms / (double)h->t_count : 0.0;
+    return GF_OK;
+}
+
+int gf_set_graph(gf_handle h, int enable) {
+    if (!h) return GF_E_INVALID;
+    h->use_graph = enable != 0;
+    h->graph.clear();
+    return GF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,476 @@
+// gf_kernels.hip -- everything besides the half-sweep: F / theta / unitarity
+// reductions in FP64 (Sec. 2.1, Sec. 4.5), per-unit stopping decisions,
+// reprojection to SU(3), layout conversion to and from the natural order,
+// the Coulomb fix-up of the temporal links, and small bookkeeping kernels.
+#include "gf_device.hpp"
+#include "gf_launch.hpp"
+
+namespace gfd {
+
+constexpr int MBLOCK = 256;
+
+// sum over a 256-thread block, result valid in thread 0 (fixed order)
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    return r;
+}
+
+__device__ __forceinline__ double block_max(double v, double *sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    return r;
+}
+
+// traceless part of (K - K^dag)/(2i): sum |.|^2
+__device__ __forceinline__ double delta_norm2(const M3<double> &K) {
+    // A = (K - K^dag)/(2i): A_ij = ((K_ij - conj K_ji)) / (2i)
+    cx<double> A[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const cx<double> d = csub(K.e[i][j], cconj(K.e[j][i]));
+            A[i][j] = cmk(0.5 * d.im, -0.5 * d.re);  // d / (2i)
+        }
+    const double tr = (A[0][0].re + A[1][1].re + A[2][2].re) / 3.0;  // trace is real
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<double> a = A[i][j];
+            if (i == j) a.re -= tr;
+            s += cnorm2(a);
+        }
+    return s;
+}
+
+__device__ __forceinline__ cx<double> det3(const M3<double> &m) {
+    cx<double> a = cmul(m.e[0][0], csub(cmul(m.e[1][1], m.e[2][2]), cmul(m.e[1][2], m.e[2][1])));
+    cx<double> b = cmul(m.e[0][1], csub(cmul(m.e[1][0], m.e[2][2]), cmul(m.e[1][2], m.e[2][0])));
+    cx<double> c = cmul(m.e[0][2], csub(cmul(m.e[1][0], m.e[2][1]), cmul(m.e[1][1], m.e[2][0])));
+    return cadd(csub(a, b), c);
+}
+
+// Per site (both parities): F contribution of the forward links, theta of
+// the site; optional |1 - det U| of the forward links.  Partials per tile.
+template <int GAUGE, int ST>
+__global__ __launch_bounds__(MBLOCK) void k_measure(gfs::MeasureArgs a) {
+    typedef Store<ST> SD;
+    constexpr int NDIR = (GAUGE == gfs::COULOMB) ? 3 : 4;
+    constexpr int MU0 = (GAUGE == gfs::COULOMB) ? 1 : 0;
+    __shared__ double sh[4];
+    const gfs::MTile tl = a.tiles[blockIdx.x];
+    const gfs::UnitDev U = a.unit[tl.unit];
+    const gfs::InstDev I = a.inst[U.inst];
+    int32_t j = tl.j0 + threadIdx.x;
+    const bool valid = j < U.n;
+    if (!valid) j = U.n - 1;
+    const int32_t h = U.h0 + j;
+    const int p = tl.parity;
+    const Site s = site_of(I, h, p);
+
+    double F = 0.0, th = 0.0, us = 0.0, um = 0.0;
+    M3<double> K;
+    m3_zero(K);  // Landau/Coulomb: K; MAG: W
+#pragma unroll
+    for (int q = 0; q < NDIR; ++q) {
+        const int mu = MU0 + q;
+        typename SD::S r[SD::NR];
+        M3<double> m;
+        SD::load(plane_ptr<ST>(a.ws, I, p, mu), I.Vh, h, r);
+        expand<ST, double>(r, m);
+        if (a.with_unitarity) {
+            const cx<double> d = det3(m);
+            const double e = sqrt((1.0 - d.re) * (1.0 - d.re) + d.im * d.im);
+            us += e;
+            um = fmax(um, e);
+        }
+        if constexpr (GAUGE == gfs::MAG) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) F += cnorm2(m.e[i][i]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) K.e[i][k] = cadd(K.e[i][k], cmulc(m.e[i][k], m.e[k][k]));
+        } else {
+            F += m.e[0][0].re + m.e[1][1].re + m.e[2][2].re;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) K.e[i][k] = cadd(K.e[i][k], m.e[i][k]);
+        }
+        SD::load(plane_ptr<ST>(a.ws, I, 1 - p, mu), I.Vh, back_h(I, s, h, mu), r);
+        expand<ST, double>(r, m);
+        if constexpr (GAUGE == gfs::MAG) {
+            // - diag(U')^dag U'
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const cx<double> t = cmul(cconj(m.e[i][i]), m.e[i][k]);
+                    K.e[i][k] = csub(K.e[i][k], t);
+                }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) K.e[i][k] = cadd(K.e[i][k], cconj(m.e[k][i]));
+        }
+    }
+    if constexpr (GAUGE == gfs::MAG) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = i + 1; k < 3; ++k) th += cnorm2(csub(K.e[i][k], cconj(K.e[k][i])));
+    } else {
+        th = delta_norm2(K);
+    }
+    if (!valid) F = th = us = um = 0.0;
+    const double bF = block_sum(F, sh);
+    const double bT = block_sum(th, sh);
+    double bU = 0.0, bM = 0.0;
+    if (a.with_unitarity) {
+        bU = block_sum(us, sh);
+        bM = block_max(um, sh);
+    }
+    if (threadIdx.x == 0) {
+        double *o = a.partial + 4 * (int64_t)blockIdx.x;
+        o[0] = bF;
+        o[1] = bT;
+        o[2] = bU;
+        o[3] = bM;
+    }
+}
+
+// One block per unit: sum the unit's tile partials in a fixed order and
+// normalise: F = sum / (3 NDIR V_u), theta = sum / (3 V_u).
+__global__ __launch_bounds__(MBLOCK) void k_finalize(const gfs::UnitDev *units, const double *partial, int ndir,
+                                                     double *out /* 4 per unit */) {
+    __shared__ double sh[4];
+    const gfs::UnitDev U = units[blockIdx.x];
+    double F = 0.0, th = 0.0, us = 0.0, um = 0.0;
+    for (int t = U.mtile0 + threadIdx.x; t < U.mtile1; t += MBLOCK) {
+        F += partial[4 * (int64_t)t];
+        th += partial[4 * (int64_t)t + 1];
+        us += partial[4 * (int64_t)t + 2];
+        um = fmax(um, partial[4 * (int64_t)t + 3]);
+    }
+    const double bF = block_sum(F, sh);
+    const double bT = block_sum(th, sh);
+    const double bU = block_sum(us, sh);
+    const double bM = block_max(um, sh);
+    if (threadIdx.x == 0) {
+        const double V = 2.0 * (double)U.n;
+        out[4 * blockIdx.x] = bF / (3.0 * ndir * V);
+        out[4 * blockIdx.x + 1] = bT / (3.0 * V);
+        out[4 * blockIdx.x + 2] = bU / (ndir * V);
+        out[4 * blockIdx.x + 3] = bM;
+    }
+}
+
+// Stopping decision after a measurement (one block): a unit stops at the
+// first check with theta < tol; counts active units, flags non-finite values,
+// sets the FP64-tail flag.  status[0] = active units, status[1] = non-finite.
+__global__ __launch_bounds__(MBLOCK) void k_decide(int nunits, const double *res, int32_t *active, int32_t *fp64,
+                                                   double tol, double tail, int32_t *status) {
+    __shared__ double sh[4];
+    double cnt = 0.0, bad = 0.0;
+    for (int u = threadIdx.x; u < nunits; u += MBLOCK) {
+        const double F = res[4 * u], th = res[4 * u + 1];
+        const bool fin = isfinite(F) && isfinite(th);
+        if (!fin) bad += 1.0;
+        if (active[u] && th < tol) active[u] = 0;
+        fp64[u] = (th < tail) ? 1 : 0;
+        cnt += active[u] ? 1.0 : 0.0;
+    }
+    const double c = block_sum(cnt, sh);
+    const double b = block_sum(bad, sh);
+    if (threadIdx.x == 0) {
+        status[0] = (int32_t)c;
+        status[1] = (int32_t)b;
+    }
+}
+
+// After every sweep: count it for the units that took part, advance the
+// random-stream index of every instance with an active unit.
+__global__ void k_count_sweep(int ninst, const gfs::InstDev *inst, const int32_t *active, int32_t *sweeps_done,
+                              uint64_t *sweep_ix) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst) return;
+    const gfs::InstDev I = inst[i];
+    int any = 0;
+    for (int u = I.unit0; u < I.unit0 + I.nunits; ++u)
+        if (active[u]) {
+            ++sweeps_done[u];
+            any = 1;
+        }
+    if (any) ++sweep_ix[i];
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------- reprojection
+// normalise row 0, Gram-Schmidt row 1, row 2 = (row0 x row1)^*  (in FP64)
+__device__ __forceinline__ void reproject(M3<double> &m) {
+    double n0 = cnorm2(m.e[0][0]) + cnorm2(m.e[0][1]) + cnorm2(m.e[0][2]);
+    n0 = 1.0 / sqrt(n0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m.e[0][k] = cmk(m.e[0][k].re * n0, m.e[0][k].im * n0);
+    cx<double> pr = cmk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pr = cadd(pr, cmulc(m.e[1][k], m.e[0][k]));  // conj(row0) . row1
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m.e[1][k] = csub(m.e[1][k], cmul(pr, m.e[0][k]));
+    double n1 = cnorm2(m.e[1][0]) + cnorm2(m.e[1][1]) + cnorm2(m.e[1][2]);
+    n1 = 1.0 / sqrt(n1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m.e[1][k] = cmk(m.e[1][k].re * n1, m.e[1][k].im * n1);
+    m3_row2(m);
+}
+
+// reproject `count` vectors-of-links: every (plane, site) of the given
+// storage region [base, base + nplanes planes of Vh sites)
+template <int ST>
+__global__ __launch_bounds__(MBLOCK) void k_reunit(char *ws, int64_t off, int32_t nplanes, int32_t Vh) {
+    typedef Store<ST> SD;
+    const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
+    if (idx >= (int64_t)nplanes * Vh) return;
+    const int32_t pl = (int32_t)(idx / Vh), h = (int32_t)(idx - (int64_t)pl * Vh);
+    typename SD::V *base = reinterpret_cast<typename SD::V *>(ws + off) + (int64_t)pl * SD::NCH * Vh;
+    typename SD::S r[SD::NR];
+    SD::load(base, Vh, h, r);
+    M3<double> m;
+    expand<ST, double>(r, m);
+    reproject(m);
+    compress<ST, double>(m, r);
+    SD::store(base, Vh, h, r);
+}
+
+// identity into the Coulomb accumulator (2 parity planes)
+template <int ST>
+__global__ __launch_bounds__(MBLOCK) void k_set_identity(char *ws, int64_t off, int32_t Vh) {
+    typedef Store<ST> SD;
+    const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
+    if (idx >= 2 * (int64_t)Vh) return;
+    const int32_t pl = (int32_t)(idx / Vh), h = (int32_t)(idx - (int64_t)pl * Vh);
+    typename SD::V *base = reinterpret_cast<typename SD::V *>(ws + off) + (int64_t)pl * SD::NCH * Vh;
+    M3<double> m;
+    m3_identity(m);
+    typename SD::S r[SD::NR];
+    compress<ST, double>(m, r);
+    SD::store(base, Vh, h, r);
+}
+
+// ---------------------------------------------------------------- layout conversion
+// natural FP64-18 links of sites [s0, s0 + ns) (src[(s - s0)*72 + mu*18 + ...])
+// into the parity-split storage
+template <int ST>
+__global__ __launch_bounds__(MBLOCK) void k_convert_in(char *ws, gfs::InstDev I, const double *src, int64_t s0,
+                                                       int64_t ns) {
+    typedef Store<ST> SD;
+    const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
+    if (idx >= ns * 4) return;
+    const int64_t k = idx >> 2;
+    const int mu = (int)(idx & 3);
+    const int64_t site = s0 + k;
+    // parity of the natural index
+    int64_t r = site;
+    const int z = (int)(r % I.n[3]);
+    r /= I.n[3];
+    const int y = (int)(r % I.n[2]);
+    r /= I.n[2];
+    const int x = (int)(r % I.n[1]);
+    const int t = (int)(r / I.n[1]);
+    const int p = (t + x + y + z) & 1;
+    const int32_t h = (int32_t)(site >> 1);
+    const double *m = src + k * 72 + mu * 18;
+    typename SD::S rr[SD::NR];
+#pragma unroll
+    for (int c = 0; c < SD::NR; ++c) rr[c] = (typename SD::S)m[c];
+    SD::store(plane_ptr<ST>(ws, I, p, mu), I.Vh, h, rr);
+}
+
+template <int ST>
+__global__ __launch_bounds__(MBLOCK) void k_convert_out(const char *ws, gfs::InstDev I, double *dst, int64_t s0,
+                                                        int64_t ns, int reunit) {
+    typedef Store<ST> SD;
+    const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
+    if (idx >= ns * 4) return;
+    const int64_t k = idx >> 2;
+    const int mu = (int)(idx & 3);
+    const int64_t site = s0 + k;
+    int64_t r = site;
+    const int z = (int)(r % I.n[3]);
+    r /= I.n[3];
+    const int y = (int)(r % I.n[2]);
+    r /= I.n[2];
+    const int x = (int)(r % I.n[1]);
+    const int t = (int)(r / I.n[1]);
+    const int p = (t + x + y + z) & 1;
+    const int32_t h = (int32_t)(site >> 1);
+    typename SD::S rr[SD::NR];
+    SD::load(plane_ptr<ST>(const_cast<char *>(ws), I, p, mu), I.Vh, h, rr);
+    M3<double> m;
+    expand<ST, double>(rr, m);
+    if (reunit) reproject(m);
+    double *o = dst + k * 72 + mu * 18;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            o[2 * (3 * i + jj)] = m.e[i][jj].re;
+            o[2 * (3 * i + jj) + 1] = m.e[i][jj].im;
+        }
+}
+
+// ---------------------------------------------------------------- Coulomb
+// U_0(x) <- G(x) U_0(x) G(x + 0)^dag for every site (the accumulated
+// transformation of each time-slice applied to the temporal links, Sec. 5)
+template <int ST>
+__global__ __launch_bounds__(MBLOCK) void k_coulomb_fix(char *ws, gfs::InstDev I) {
+    typedef Store<ST> SD;
+    const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
+    if (idx >= 2 * (int64_t)I.Vh) return;
+    const int p = (int)(idx / I.Vh);
+    const int32_t h = (int32_t)(idx - (int64_t)p * I.Vh);
+    const Site s = site_of(I, h, p);
+    typename SD::S r[SD::NR];
+    M3<double> gx, gy, u, t, o;
+    SD::load(gacc_ptr<ST>(ws, I, p), I.Vh, h, r);
+    expand<ST, double>(r, gx);
+    SD::load(gacc_ptr<ST>(ws, I, 1 - p), I.Vh, fwd_h(I, s, h, 0), r);
+    expand<ST, double>(r, gy);
+    SD::load(plane_ptr<ST>(ws, I, p, 0), I.Vh, h, r);
+    expand<ST, double>(r, u);
+    apply_left3(gx, u, t);
+    apply_right_dag3(gy, t, o);
+    compress<ST, double>(o, r);
+    SD::store(plane_ptr<ST>(ws, I, p, 0), I.Vh, h, r);
+}
+
+}  // namespace gfd
+
+// ---------------------------------------------------------------- launchers
+namespace gfl {
+
+using namespace gfd;
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + MBLOCK - 1) / MBLOCK); }
+
+template <int G>
+static hipError_t measure_g(int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a) {
+    if (st == gfs::ST_F64R18)
+        k_measure<G, gfs::ST_F64R18><<<ntiles, MBLOCK, 0, s>>>(a);
+    else if (st == gfs::ST_F64R12)
+        k_measure<G, gfs::ST_F64R12><<<ntiles, MBLOCK, 0, s>>>(a);
+    else
+        k_measure<G, gfs::ST_F32R12><<<ntiles, MBLOCK, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t measure(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a) {
+    if (ntiles == 0) return hipSuccess;
+    if (gauge == gfs::LANDAU) return measure_g<gfs::LANDAU>(st, ntiles, s, a);
+    if (gauge == gfs::COULOMB) return measure_g<gfs::COULOMB>(st, ntiles, s, a);
+    return measure_g<gfs::MAG>(st, ntiles, s, a);
+}
+
+hipError_t finalize(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, double *out,
+                    hipStream_t s) {
+    k_finalize<<<nunits, MBLOCK, 0, s>>>(units, partial, ndir, out);
+    return hipGetLastError();
+}
+
+hipError_t decide(int nunits, const double *res, int32_t *active, int32_t *fp64, double tol, double tail,
+                  int32_t *status, hipStream_t s) {
+    k_decide<<<1, MBLOCK, 0, s>>>(nunits, res, active, fp64, tol, tail, status);
+    return hipGetLastError();
+}
+
+hipError_t count_sweep(int ninst, const gfs::InstDev *inst, const int32_t *active, int32_t *sweeps_done,
+                       uint64_t *sweep_ix, hipStream_t s) {
+    k_count_sweep<<<(ninst + 63) / 64, 64, 0, s>>>(ninst, inst, active, sweeps_done, sweep_ix);
+    return hipGetLastError();
+}
+
+hipError_t fill_i32(int32_t *p, int32_t v, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_fill_i32<<<(n + 255) / 256, 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, hipStream_t s) {
+    const int64_t n = (int64_t)nplanes * Vh;
+    if (st == gfs::ST_F64R18)
+        k_reunit<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh);
+    else if (st == gfs::ST_F64R12)
+        k_reunit<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh);
+    else
+        k_reunit<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh);
+    return hipGetLastError();
+}
+
+hipError_t set_identity(int st, char *ws, int64_t off, int32_t Vh, hipStream_t s) {
+    const int64_t n = 2 * (int64_t)Vh;
+    if (st == gfs::ST_F64R18)
+        k_set_identity<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, off, Vh);
+    else if (st == gfs::ST_F64R12)
+        k_set_identity<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, Vh);
+    else
+        k_set_identity<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, Vh);
+    return hipGetLastError();
+}
+
+hipError_t convert_in(int st, char *ws, const gfs::InstDev &I, const double *src, int64_t s0, int64_t ns,
+                      hipStream_t s) {
+    const int64_t n = 4 * ns;
+    if (st == gfs::ST_F64R18)
+        k_convert_in<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, I, src, s0, ns);
+    else if (st == gfs::ST_F64R12)
+        k_convert_in<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, I, src, s0, ns);
+    else
+        k_convert_in<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, I, src, s0, ns);
+    return hipGetLastError();
+}
+
+hipError_t convert_out(int st, const char *ws, const gfs::InstDev &I, double *dst, int64_t s0, int64_t ns, int reunit,
+                       hipStream_t s) {
+    const int64_t n = 4 * ns;
+    if (st == gfs::ST_F64R18)
+        k_convert_out<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, I, dst, s0, ns, reunit);
+    else if (st == gfs::ST_F64R12)
+        k_convert_out<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, I, dst, s0, ns, reunit);
+    else
+        k_convert_out<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, I, dst, s0, ns, reunit);
+    return hipGetLastError();
+}
+
+hipError_t coulomb_fix(int st, char *ws, const gfs::InstDev &I, hipStream_t s) {
+    const int64_t n = 2 * (int64_t)I.Vh;
+    if (st == gfs::ST_F64R18)
+        k_coulomb_fix<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, I);
+    else if (st == gfs::ST_F64R12)
+        k_coulomb_fix<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, I);
+    else
+        k_coulomb_fix<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, I);
+    return hipGetLastError();
+}
+
+}  // namespace gfl

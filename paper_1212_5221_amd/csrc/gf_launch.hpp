@@ -1,0 +1,36 @@
+// gf_launch.hpp -- host-side launchers of the libgf kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gf_shared.hpp"
+
+namespace gfl {
+
+// the half-sweep kernel variant for (gauge, update, storage, compute in
+// double?, waves per site group); nullptr if not built
+typedef void (*sweep_fn)(gfs::SweepArgs);
+sweep_fn sweep_kernel(int gauge, int upd, int st, int ct_double, int W);
+sweep_fn sweep_kernel_landau(int upd, int st, int ct_double, int W);
+sweep_fn sweep_kernel_coulomb(int upd, int st, int ct_double, int W);
+sweep_fn sweep_kernel_mag(int upd, int st, int ct_double, int W);
+constexpr int SWEEP_THREADS = 256;
+
+hipError_t measure(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a);
+hipError_t finalize(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, double *out,
+                    hipStream_t s);
+hipError_t decide(int nunits, const double *res, int32_t *active, int32_t *fp64, double tol, double tail,
+                  int32_t *status, hipStream_t s);
+hipError_t count_sweep(int ninst, const gfs::InstDev *inst, const int32_t *active, int32_t *sweeps_done,
+                       uint64_t *sweep_ix, hipStream_t s);
+hipError_t fill_i32(int32_t *p, int32_t v, int n, hipStream_t s);
+hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, hipStream_t s);
+hipError_t set_identity(int st, char *ws, int64_t off, int32_t Vh, hipStream_t s);
+hipError_t convert_in(int st, char *ws, const gfs::InstDev &I, const double *src, int64_t s0, int64_t ns,
+                      hipStream_t s);
+hipError_t convert_out(int st, const char *ws, const gfs::InstDev &I, double *dst, int64_t s0, int64_t ns, int reunit,
+                       hipStream_t s);
+hipError_t coulomb_fix(int st, char *ws, const gfs::InstDev &I, hipStream_t s);
+
+}  // namespace gfl

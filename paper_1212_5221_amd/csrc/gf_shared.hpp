@@ -1,0 +1,71 @@
+// gf_shared.hpp -- plain structs and enums shared by the host library and the
+// HIP kernels of libgf (never by the CPU oracle).
+#pragma once
+
+#include <stdint.h>
+
+namespace gfs {
+
+enum Gauge { LANDAU = 0, COULOMB = 1, MAG = 2 };
+enum Update { UPD_OR = 0, UPD_MICRO = 1, UPD_HEATBATH = 2, UPD_SR = 3 };
+enum Storage { ST_F64R18 = 0, ST_F64R12 = 1, ST_F32R12 = 2 };
+
+// one lattice instance, as the kernels see it
+struct InstDev {
+    int32_t n[4];      // Nt, Nx, Ny, Nz
+    int32_t Vh;        // half the number of sites
+    int32_t unit0;     // first unit of this instance
+    int32_t nunits;    // 1 (Landau, MAG) or Nt (Coulomb)
+    int32_t pad;
+    int64_t links_off; // byte offset of the link planes in the workspace
+    int64_t g_off;     // byte offset of the Coulomb accumulator (or -1)
+};
+
+// one independently stopping unit: a whole instance, or one Coulomb time-slice
+struct UnitDev {
+    int32_t inst;
+    int32_t t;       // time-slice (Coulomb) or -1
+    int32_t h0;      // first half-site index of the unit
+    int32_t n;       // half-sites of the unit (sites of one parity)
+    int32_t mtile0;  // measure tiles [mtile0, mtile1) belong to this unit
+    int32_t mtile1;
+};
+
+// a sweep tile: sites [j0, j0 + sites_per_block) of one unit
+struct Tile {
+    int32_t unit;
+    int32_t j0;
+};
+
+// a measure tile: sites [j0, j0 + 256) of parity p of one unit
+struct MTile {
+    int32_t unit;
+    int32_t parity;
+    int32_t j0;
+    int32_t pad;
+};
+
+struct SweepArgs {
+    char *ws;
+    const InstDev *inst;
+    const UnitDev *unit;
+    const Tile *tiles;
+    const int32_t *active;    // per unit
+    const int32_t *fp64;      // per unit: tail flag (mixed storage)
+    const uint64_t *sweep_ix; // per instance: global sweep index (random counter)
+    int32_t parity;           // active parity (Coulomb: 3D parity)
+    int32_t fp64_select;      // -1 all units, else only units whose flag equals it
+    double omega, T, p_sr;
+    uint64_t seed;
+};
+
+struct MeasureArgs {
+    char *ws;
+    const InstDev *inst;
+    const UnitDev *unit;
+    const MTile *tiles;
+    double *partial; // 4 doubles per measure tile: F, theta, sum |1-det|, max |1-det|
+    int32_t with_unitarity;
+};
+
+}  // namespace gfs

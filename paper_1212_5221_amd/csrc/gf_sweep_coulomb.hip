@@ -1,0 +1,39 @@
+// gf_sweep_coulomb.hip -- half-sweep kernel variants for the coulomb gauge.
+#include "gf_launch.hpp"
+#include "gf_sweep.hpp"
+
+namespace gfl {
+
+sweep_fn sweep_kernel_coulomb(int upd, int st, int ctd, int W) {
+    if (W == 1 && upd == gfs::UPD_OR && st == gfs::ST_F64R18 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_OR, gfs::ST_F64R18, double, 1>;
+    if (W == 1 && upd == gfs::UPD_OR && st == gfs::ST_F64R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_OR, gfs::ST_F64R12, double, 1>;
+    if (W == 1 && upd == gfs::UPD_OR && st == gfs::ST_F32R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_OR, gfs::ST_F32R12, double, 1>;
+    if (W == 1 && upd == gfs::UPD_OR && st == gfs::ST_F32R12 && !ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_OR, gfs::ST_F32R12, float, 1>;
+    if (W == 1 && upd == gfs::UPD_MICRO && st == gfs::ST_F64R18 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_MICRO, gfs::ST_F64R18, double, 1>;
+    if (W == 1 && upd == gfs::UPD_MICRO && st == gfs::ST_F64R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_MICRO, gfs::ST_F64R12, double, 1>;
+    if (W == 1 && upd == gfs::UPD_MICRO && st == gfs::ST_F32R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_MICRO, gfs::ST_F32R12, double, 1>;
+    if (W == 1 && upd == gfs::UPD_MICRO && st == gfs::ST_F32R12 && !ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_MICRO, gfs::ST_F32R12, float, 1>;
+    if (W == 1 && upd == gfs::UPD_HEATBATH && st == gfs::ST_F64R18 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_HEATBATH, gfs::ST_F64R18, double, 1>;
+    if (W == 1 && upd == gfs::UPD_HEATBATH && st == gfs::ST_F64R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_HEATBATH, gfs::ST_F64R12, double, 1>;
+    if (W == 1 && upd == gfs::UPD_HEATBATH && st == gfs::ST_F32R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_HEATBATH, gfs::ST_F32R12, double, 1>;
+    if (W == 1 && upd == gfs::UPD_SR && st == gfs::ST_F64R18 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_SR, gfs::ST_F64R18, double, 1>;
+    if (W == 1 && upd == gfs::UPD_SR && st == gfs::ST_F64R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_SR, gfs::ST_F64R12, double, 1>;
+    if (W == 1 && upd == gfs::UPD_SR && st == gfs::ST_F32R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_SR, gfs::ST_F32R12, double, 1>;
+    if (W == 2 && upd == gfs::UPD_OR && st == gfs::ST_F64R18 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_OR, gfs::ST_F64R18, double, 2>;
+    if (W == 2 && upd == gfs::UPD_OR && st == gfs::ST_F64R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_OR, gfs::ST_F64R12, double, 2>;
+    if (W == 2 && upd == gfs::UPD_OR && st == gfs::ST_F32R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_OR, gfs::ST_F32R12, double, 2>;
+    if (W == 2 && upd == gfs::UPD_OR && st == gfs::ST_F32R12 && !ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_OR, gfs::ST_F32R12, float, 2>;
+    if (W == 2 && upd == gfs::UPD_MICRO && st == gfs::ST_F64R18 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_MICRO, gfs::ST_F64R18, double, 2>;
+    if (W == 2 && upd == gfs::UPD_MICRO && st == gfs::ST_F64R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_MICRO, gfs::ST_F64R12, double, 2>;
+    if (W == 2 && upd == gfs::UPD_MICRO && st == gfs::ST_F32R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_MICRO, gfs::ST_F32R12, double, 2>;
+    if (W == 2 && upd == gfs::UPD_MICRO && st == gfs::ST_F32R12 && !ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_MICRO, gfs::ST_F32R12, float, 2>;
+    if (W == 2 && upd == gfs::UPD_HEATBATH && st == gfs::ST_F64R18 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_HEATBATH, gfs::ST_F64R18, double, 2>;
+    if (W == 2 && upd == gfs::UPD_HEATBATH && st == gfs::ST_F64R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_HEATBATH, gfs::ST_F64R12, double, 2>;
+    if (W == 2 && upd == gfs::UPD_HEATBATH && st == gfs::ST_F32R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_HEATBATH, gfs::ST_F32R12, double, 2>;
+    if (W == 2 && upd == gfs::UPD_SR && st == gfs::ST_F64R18 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_SR, gfs::ST_F64R18, double, 2>;
+    if (W == 2 && upd == gfs::UPD_SR && st == gfs::ST_F64R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_SR, gfs::ST_F64R12, double, 2>;
+    if (W == 2 && upd == gfs::UPD_SR && st == gfs::ST_F32R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_SR, gfs::ST_F32R12, double, 2>;
+    return nullptr;
+}
+
+}  // namespace gfl

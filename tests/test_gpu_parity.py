@@ -1,0 +1,250 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Small lattices with ragged last tiles (sites of one parity not a multiple of
+the tile size), every gauge, update type and link storage.
+Tolerances: FP64 storage 1e-12 on links after one sweep (rounding order
+differs: the GPU applies the product of the three subgroup elements once).
+Mixed storage computes the update in FP32 from FP32 links: K is a sum of up
+to 8 SU(3) matrices (|K_ij| <= 8, ulp(8) = 9.5e-7), so the relaxation
+direction carries errors of a few ulp(8), amplified up to 2x by the
+microcanonical square; the bound is 3e-5 (about thirty ulp(8)).  With the
+update computed in FP64 (the FP64 tail) only the FP32 rounding of the
+stored links remains: a few ulp(1) = 6e-8 per update, bound 1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1212_5221_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+STORAGES = ["f64r18", "f64r12", "mixed"]
+ALL_MODES = STORAGES + ["mixed64"]  # mixed64: FP32 storage, update in FP64
+TOL_LINK = {"f64r18": 1e-12, "f64r12": 1e-12, "mixed": 3e-5, "mixed64": 1e-6}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def fixer(dims_list, gauge, storage, **kw):
+    from paper_1212_5221_amd import gf
+    if storage == "mixed64":
+        storage = "mixed"
+        kw["tail_theta"] = 1e300  # FP64 update everywhere
+    return gf.GaugeFixer(dims_list, gauge=gauge, storage=storage, **kw)
+
+
+def f32_round(U):
+    """the input as the mixed storage holds it (rows 0, 1 rounded to FP32, row 2 rebuilt in FP64)"""
+    C = U[..., 0].astype(np.float32).astype(np.float64) + 1j * U[..., 1].astype(np.float32).astype(np.float64)
+    u, v = C[..., 0, :], C[..., 1, :]
+    w = np.conj(np.cross(u, v))
+    C = np.stack([u, v, w], axis=-2)
+    return np.ascontiguousarray(np.stack([C.real, C.imag], axis=-1))
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+def test_roundtrip(storage):
+    dims = (4, 6, 2, 8)
+    say("roundtrip", storage, dims)
+    U = I.smooth(dims, 0.5, 7)
+    fx = fixer([dims], "landau", storage)
+    fx.upload(0, U)
+    D = fx.download(0)
+    if storage == "f64r18":
+        np.testing.assert_array_equal(D, U)
+    elif storage == "f64r12":
+        np.testing.assert_allclose(D, U, atol=1e-15)
+    else:
+        np.testing.assert_allclose(D, U, atol=1e-7)
+    # slabs
+    part = fx.download(0, t0=1, nt=2)
+    vs = 6 * 2 * 8
+    np.testing.assert_array_equal(part, D[vs:3 * vs])
+    fx.upload(0, U[vs:2 * vs] * 0 + U[0:vs], t0=1, nt=1)
+    D2 = fx.download(0)
+    np.testing.assert_array_equal(D2[vs:2 * vs], D[0:vs])
+    fx.close()
+
+
+def _run_halfsweeps(gauge, update, storage, dims, seed, T=0.7, omega=1.7, p=0.5):
+    U = I.smooth(dims, 0.6, seed)
+    fx = fixer([dims], gauge, storage)
+    fx.upload(0, U)
+    fx.set_overrelax(omega)
+    fx.set_seed(77)
+    fx.set_temperature(T)
+    fx.set_stochastic(p)
+    ref = f32_round(U) if storage.startswith("mixed") else U.copy()
+    V = int(np.prod(dims))
+    G = O.identity_field(V) if gauge == "coulomb" else None
+    for parity in (0, 1):
+        say("halfsweep", gauge, update, storage, dims, "parity", parity)
+        fx.halfsweep(update, parity)
+        O.halfsweep(ref, dims, gauge, update, parity, omega=omega, T=T, p_sr=p, seed=77, instance=0, sweep=0, G=G)
+    out = fx.download(0)
+    fx.close()
+    return out, ref
+
+
+@pytest.mark.parametrize("storage", ALL_MODES)
+@pytest.mark.parametrize("gauge", ["landau", "coulomb", "mag"])
+@pytest.mark.parametrize("update", ["or", "micro"])
+def test_halfsweep_matches_oracle(gauge, update, storage):
+    dims = (6, 4, 6, 4)  # 288 sites per parity: a full and a ragged tile
+    out, ref = _run_halfsweeps(gauge, update, storage, dims, 11)
+    err = np.max(np.abs(out - ref))
+    say("max |gpu - oracle| =", err)
+    assert err < TOL_LINK[storage]
+
+
+@pytest.mark.parametrize("storage", ["f64r18", "f64r12"])
+@pytest.mark.parametrize("gauge", ["landau", "coulomb", "mag"])
+@pytest.mark.parametrize("update", ["heatbath", "sr"])
+def test_random_updates_match_oracle(gauge, update, storage):
+    dims = (4, 4, 6, 4)
+    out, ref = _run_halfsweeps(gauge, update, storage, dims, 12)
+    err = np.max(np.abs(out - ref))
+    say("max |gpu - oracle| =", err)
+    assert err < 1e-11
+
+
+def _trajectory_gpu(fx, nsweeps):
+    F, th = [], []
+    for k in range(nsweeps + 1):
+        f, t = fx.measure(0)
+        F.append(f)
+        th.append(t)
+        if k < nsweeps:
+            fx.sweep("or", max_sweeps=1, tol=0.0, check_every=1)
+    return np.array(F), np.array(th)
+
+
+@pytest.mark.parametrize("storage", ["f64r18", "f64r12"])
+def test_c1_landau_trajectory(storage):
+    # 8^4, eps = 0.3, seed 1001, omega = 1.7: F and theta after every sweep
+    dims = (8, 8, 8, 8)
+    say("C1 trajectory", storage)
+    U = I.smooth(dims, 0.3, 1001)
+    r = O.run(U.copy(), dims, "landau", "or", omega=1.7, max_sweeps=2000, tol=1e-14, check_every=1)
+    n = int(r.sweeps_done[0])
+    fx = fixer([dims], "landau", storage)
+    fx.upload(0, U)
+    fx.set_overrelax(1.7)
+    F, th = _trajectory_gpu(fx, n)
+    fx.close()
+    relF = np.max(np.abs(F - r.F) / np.abs(r.F))
+    dth = np.abs(th - r.theta)
+    bound = 1e-10 * r.theta + 1e-13 * np.sqrt(r.theta) + 1e-18
+    say("sweeps", n, "max rel dF", relF, "max dtheta/bound", np.max(dth / bound))
+    assert relF < 1e-10
+    assert np.all(dth <= bound)
+
+
+@pytest.mark.parametrize("gauge", ["landau", "coulomb", "mag"])
+def test_full_run_matches_oracle(gauge):
+    dims = (4, 6, 4, 6)
+    say("full run", gauge)
+    U = I.smooth(dims, 0.5, 21)
+    ref = U.copy()
+    r = O.run(ref, dims, gauge, "or", omega=1.7, max_sweeps=3000, tol=1e-12, check_every=5)
+    fx = fixer([dims], gauge, "f64r18")
+    fx.upload(0, U)
+    fx.set_overrelax(1.7)
+    st, done = fx.sweep("or", max_sweeps=3000, tol=1e-12, check_every=5)
+    out = fx.download(0)
+    F, th = fx.measure(0)
+    fx.close()
+    say("oracle sweeps", r.sweeps_done.tolist(), "gpu", done.tolist())
+    assert st == 0 and r.status == 0
+    np.testing.assert_array_equal(done, r.sweeps_done.astype(np.int32))
+    Fo, tho = O.measure(ref, dims, gauge)
+    assert abs(F - Fo) < 1e-12 and th < 1e-12
+    assert np.max(np.abs(out - ref)) < 1e-9
+
+
+@pytest.mark.parametrize("gauge", ["landau", "coulomb", "mag"])
+@pytest.mark.parametrize("storage", ALL_MODES)
+def test_pure_gauge_reaches_F_one(gauge, storage):
+    # FP32 storage drifts off SU(3) (Sec. 4.5): reproject every 10 sweeps and
+    # once at the end, in FP64, as the mixed scheme prescribes
+    dims = (4, 4, 4, 4)
+    say("pure gauge", gauge, storage)
+    mixed = storage.startswith("mixed")
+    fx = fixer([dims], gauge, storage, reunit_every=10 if mixed else 0)
+    fx.upload(0, I.pure_gauge(dims, 1002))
+    fx.set_overrelax(1.7)
+    tol = 1e-14 if not mixed else 1e-12
+    st, done = fx.sweep("or", max_sweeps=3000, tol=tol, check_every=5)
+    if mixed:
+        fx.reunitarise()
+    F, th = fx.measure(0)
+    fx.close()
+    assert st == 0
+    # FP32 links: Re tr U of each link off by about 1e-7, averaged over 1024 links
+    assert abs(F - 1) < (1e-12 if not mixed else 1e-6)
+
+
+def test_batched_uneven_instances_match_single_runs():
+    dl = [(4, 4, 4, 4), (6, 4, 2, 4), (4, 2, 6, 2)]
+    say("batch", dl)
+    Us = [I.smooth(d, 0.5, 31 + k) for k, d in enumerate(dl)]
+    fx = fixer(dl, "landau", "f64r18")
+    for k, U in enumerate(Us):
+        fx.upload(k, U)
+    fx.set_overrelax(1.7)
+    st, done = fx.sweep("or", max_sweeps=2000, tol=1e-12, check_every=3)
+    assert st == 0
+    for k, (d, U) in enumerate(zip(dl, Us)):
+        ref = U.copy()
+        r = O.run(ref, d, "landau", "or", omega=1.7, max_sweeps=2000, tol=1e-12, check_every=3)
+        assert done[k] == r.sweeps_done[0]
+        assert np.max(np.abs(fx.download(k) - ref)) < 1e-9
+    fx.close()
+
+
+def test_coulomb_per_slice_stopping_matches_oracle():
+    dims = (4, 4, 4, 4)
+    say("coulomb per-slice stop")
+    U = I.smooth(dims, 0.5, 3003)
+    U[2 * 64:3 * 64] = I.pure_gauge(dims, 5)[2 * 64:3 * 64]
+    ref = U.copy()
+    r = O.run(ref, dims, "coulomb", "or", omega=1.7, max_sweeps=2000, tol=1e-12, check_every=5)
+    fx = fixer([dims], "coulomb", "f64r18")
+    fx.upload(0, U)
+    fx.set_overrelax(1.7)
+    st, done = fx.sweep("or", max_sweeps=2000, tol=1e-12, check_every=5)
+    Ft, tht = fx.measure_timeslices(0)
+    out = fx.download(0)
+    fx.close()
+    np.testing.assert_array_equal(done, r.sweeps_done.astype(np.int32))
+    Fo, tho = O.measure_slices(ref, dims)
+    np.testing.assert_allclose(Ft, Fo, rtol=1e-12)
+    assert np.max(np.abs(out - ref)) < 1e-9  # includes the U_0 fix-up
+
+
+def test_error_paths():
+    from paper_1212_5221_amd import gf
+    say("error paths")
+    with pytest.raises(gf.GFError) as e:
+        gf.GaugeFixer([(4, 3, 4, 4)])
+    assert e.value.code == gf.E_DIMS
+    fx = fixer([(4, 4, 4, 4)], "landau", "f64r18")
+    with pytest.raises(gf.GFError) as e:
+        fx.set_overrelax(2.0)
+    assert e.value.code == gf.E_INVALID
+    U = I.smooth((4, 4, 4, 4), 0.5, 1)
+    fx.upload(0, U)
+    st, done = fx.sweep("or", max_sweeps=1, tol=1e-12)
+    assert st == gf.NOT_CONVERGED and done[0] == 1
+    U[5, 2, 0, 0, 0] = np.nan
+    fx.upload(0, U)
+    with pytest.raises(gf.GFError) as e:
+        fx.sweep("or", max_sweeps=10, tol=1e-12)
+    assert e.value.code == gf.E_NONFINITE
+    fx.close()
