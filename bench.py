@@ -1,0 +1,210 @@
+"""Benchmark: Landau-gauge overrelaxation on 32^4, mixed precision vs FP64.
+
+Workload (one GPU): smooth SU(3) configurations U_mu(x) = h(x) exp(i 0.5
+sum_a lambda_a xi_a) h(x+mu)^dag on a 32^4 lattice, seeds 2001-2004, fixed to
+Landau gauge by overrelaxation (omega = 1.7) until theta < 1e-12, checked
+every 10 sweeps.
+
+A step is one complete gauge fixing of one configuration (seeds in turn):
+layout conversion of the device-resident natural-order FP64 input into the
+FP32 12-real storage, the sweeps with their F/theta checks, and the final
+FP64 reprojection and measurement.  The metric is OR site-updates per second
+over the timed steps (sweeps x V / time); the line also carries the effective
+HBM bandwidth, time-to-theta of the mixed and the plain FP64 (12-real) GPU
+paths, the roofline of the half-sweep kernel (timed with HIP events on the
+launch stream) and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+DIMS = (32, 32, 32, 32)
+EPS = 0.5
+SEEDS = (2001, 2002, 2003, 2004)
+OMEGA = 1.7
+TOL = 1e-12
+CHECK = 10
+REUNIT = 100
+TAIL = 1e-9          # FP64 update once theta < 1e-9
+MAX_SWEEPS = 50000
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SITE = {"mixed": 768, "f64r12": 1536, "f64r18": 2304}  # 8 links loaded + stored
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_fixer(gf, storage):
+    tail = TAIL if storage == "mixed" else 0.0
+    fx = gf.GaugeFixer([DIMS], gauge="landau", storage=storage, reunit_every=REUNIT if storage == "mixed" else 0,
+                       tail_theta=tail)
+    fx.set_overrelax(OMEGA)
+    return fx
+
+
+def one_fix(fx, inp):
+    """upload (device-resident natural layout) + fix + final FP64 reprojection; returns sweeps"""
+    fx.upload(0, inp)
+    st, done = fx.sweep("or", max_sweeps=MAX_SWEEPS, tol=TOL, check_every=CHECK)
+    if fx.storage == 2:
+        fx.reunitarise()
+    return st, int(done[0])
+
+
+def cpu_baseline(budget_s=12.0):
+    """The oracle (FP64, OpenMP over the host cores) on a bounded sample: OR
+    sweeps of the seed-2001 configuration until about budget_s seconds."""
+    import oracle as O
+    from paper_1212_5221_amd import inputs as I
+    U = I.smooth(DIMS, EPS, SEEDS[0])
+    V = int(np.prod(DIMS))
+    O.sweep(U, DIMS, "landau", "or", omega=OMEGA)  # warm-up (thread pool, pages)
+    n = 0
+    t0 = time.time()
+    while True:
+        O.sweep(U, DIMS, "landau", "or", omega=OMEGA)
+        n += 1
+        if time.time() - t0 > budget_s and n >= 2:
+            break
+    el = time.time() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": V * n / el, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d Landau OR sweeps (omega 1.7) of the 32^4 seed-2001 configuration, FP64, %.1f s" % (n, el)}
+
+
+def golden_F():
+    p = os.path.join(ROOT, "tests", "golden", "c2_landau_oracle.json")
+    if not os.path.exists(p):
+        return {}
+    d = json.load(open(p))
+    return {int(k): v for k, v in d.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the gauge-fixing path is not sharded across GPUs); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1212_5221_amd import gf, inputs as I
+
+    dev = torch.device("cuda:0")
+    V = int(np.prod(DIMS))
+    log("generating inputs", DIMS, "seeds", SEEDS)
+    inputs = [torch.from_numpy(I.smooth(DIMS, EPS, s).reshape(-1)).to(dev) for s in SEEDS]
+    torch.cuda.synchronize()
+
+    fx = make_fixer(gf, "mixed")
+    lanes, _ = fx.autotune(reps=2)
+    log("autotune: waves per site group", lanes)
+    for w in range(args.warmup):
+        one_fix(fx, inputs[w % len(SEEDS)])
+    torch.cuda.synchronize()
+
+    # ---- timed region: K complete fixes, kernel timing on (HIP events on the launch stream)
+    fx.set_timing(True)
+    sweeps = []
+    status = []
+    per_step = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        st, n = one_fix(fx, inputs[k % len(SEEDS)])
+        per_step.append(time.perf_counter() - ts)
+        sweeps.append(n)
+        status.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    launches, mean_ms = fx.kernel_time("fp32")    # the dominant kernel: FP32 update
+    launches64, mean_ms64 = fx.kernel_time("fp64")  # FP64 tail
+    fx.set_timing(False)
+
+    gold = golden_F()
+    F_err = {}
+    for i, s in enumerate(SEEDS):
+        if i < args.steps and s in gold:
+            one_fix(fx, inputs[i])
+            F, th = fx.measure(0)
+            F_err[str(s)] = {"F": F, "theta": th, "F_oracle": gold[s]["F"],
+                             "rel_err": abs(F - gold[s]["F"]) / gold[s]["F"]}
+    fx.close()
+
+    site_updates = V * float(sum(sweeps))
+    value = site_updates / elapsed
+    bytes_per_launch = BYTES_PER_SITE["mixed"] * V / 2
+    achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9 if mean_ms > 0 else 0.0
+    eff_gbs = site_updates * BYTES_PER_SITE["mixed"] / elapsed / 1e9
+
+    # ---- plain FP64 GPU path: time to theta < 1e-12 per seed
+    ttt = {"mixed_s": [round(t, 4) for t in per_step[:len(SEEDS)]], "mixed_sweeps": sweeps[:len(SEEDS)]}
+    if not args.no_fp64:
+        f64 = make_fixer(gf, "f64r12")
+        one_fix(f64, inputs[0])
+        tt, sw = [], []
+        for i in range(min(args.steps, len(SEEDS))):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            st, n = one_fix(f64, inputs[i])
+            torch.cuda.synchronize()
+            tt.append(round(time.perf_counter() - ts, 4))
+            sw.append(n)
+        f64.close()
+        ttt["fp64_s"] = tt
+        ttt["fp64_sweeps"] = sw
+        ttt["speedup_mixed_vs_fp64"] = round(sum(tt) / sum(per_step[:len(tt)]), 3)
+
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    line = {
+        "metric": "OR site-updates/s (Landau, mixed FP32-12 storage, to theta<1e-12)",
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "landau-32^4-eps0.5-seeds2001-2004-omega1.7-theta1e-12", "lattice": list(DIMS),
+                   "gauge": "landau", "storage": "fp32-12real", "fp64": "reductions, reprojection every %d, update "
+                   "once theta<%g" % (REUNIT, TAIL), "check_every": CHECK, "waves_per_site_group": lanes,
+                   "status": status, "sweeps": sweeps},
+        "hbm_gbs_effective": eff_gbs,
+        "time_to_theta": ttt,
+        "F_vs_oracle": F_err,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_sweep (half-sweep)", "bytes_per_launch": bytes_per_launch,
+                     "mean_launch_ms": mean_ms, "launches": launches,
+                     "fp64_tail_launches": launches64, "fp64_tail_mean_ms": mean_ms64},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -190,11 +190,12 @@ int gf_set_launch(gf_handle h, int lanes_per_site, int block);
 int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block);
 
 /* Kernel timing: while enabled, every half-sweep launch is bracketed by HIP
-   events on the handle's stream.  gf_kernel_time returns the number of
-   timed half-sweep launches and their mean duration in milliseconds since
-   timing was last enabled. */
+   events on the handle's stream (HIP graphs are not used meanwhile).
+   gf_kernel_time returns the number of timed half-sweep launches and their
+   mean duration in milliseconds since timing was last enabled; which: 0 all
+   launches, 1 launches computing the update in FP32, 2 in FP64. */
 int gf_set_timing(gf_handle h, int enable);
-int gf_kernel_time(gf_handle h, int64_t *launches, double *mean_ms);
+int gf_kernel_time(gf_handle h, int which, int64_t *launches, double *mean_ms);
 
 /* HIP graph capture of the sweep loop between checks (1 = on, default). */
 int gf_set_graph(gf_handle h, int enable);

@@ -80,12 +80,19 @@ struct gf_ctx {
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
-    double t_sum_ms = 0.0;
-    int64_t t_count = 0;
+    struct Pending {
+        hipEvent_t e0, e1;
+        int ctd;  // compute precision of the timed launch: 0 FP32, 1 FP64
+    };
+    std::vector<Pending> ev_pending;
+    double t_sum_ms[2] = {0.0, 0.0};
+    int64_t t_count[2] = {0, 0};
 
     bool use_graph = true;
     GraphCache graph;
+
+    // from the last check: active units, of which in the FP64 tail
+    int n_active = 0, n_tail = 0;
 };
 
 namespace {
@@ -314,11 +321,11 @@ int drain_timing(gf_ctx *h) {
     HIPCHK(h, hipStreamSynchronize(h->stream));
     for (auto &p : h->ev_pending) {
         float ms = 0.f;
-        HIPCHK(h, hipEventElapsedTime(&ms, p.first, p.second));
-        h->t_sum_ms += ms;
-        h->t_count += 1;
-        h->ev_pool.push_back(p.first);
-        h->ev_pool.push_back(p.second);
+        HIPCHK(h, hipEventElapsedTime(&ms, p.e0, p.e1));
+        h->t_sum_ms[p.ctd] += ms;
+        h->t_count[p.ctd] += 1;
+        h->ev_pool.push_back(p.e0);
+        h->ev_pool.push_back(p.e1);
     }
     h->ev_pending.clear();
     return GF_OK;
@@ -337,8 +344,15 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing) {
     if (!mixed || hb) {
         launches[nl++] = {1, -1};
     } else if (h->tail_theta > 0.0) {
-        launches[nl++] = {0, 0};
-        launches[nl++] = {1, 1};
+        // only the variants some active unit needs (counts of the last check)
+        if (h->n_tail == 0)
+            launches[nl++] = {0, -1};
+        else if (h->n_tail >= h->n_active)
+            launches[nl++] = {1, -1};
+        else {
+            launches[nl++] = {0, 0};
+            launches[nl++] = {1, 1};
+        }
     } else {
         launches[nl++] = {0, -1};
     }
@@ -359,7 +373,7 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing) {
         HIPCHK(h, hipGetLastError());
         if (tm) {
             HIPCHK(h, hipEventRecord(e1, h->cur));
-            h->ev_pending.push_back({e0, e1});
+            h->ev_pending.push_back({e0, e1, launches[k].ctd});
             if (h->ev_pending.size() > 4096) {
                 int rc = drain_timing(h);
                 if (rc) return rc;
@@ -412,8 +426,10 @@ int launch_decide(gf_ctx *h, double tol) {
 }
 
 int read_status(gf_ctx *h) {
-    HIPCHK(h, hipMemcpyAsync(h->hstat, h->ws + h->off_status, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->hstat, h->ws + h->off_status, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->n_active = h->hstat[0];
+    h->n_tail = h->hstat[2];
     return GF_OK;
 }
 
@@ -443,7 +459,9 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
         }
         return GF_OK;
     }
-    const int tailkey = (h->storage == GF_MIXED_F32_R12 && h->tail_theta > 0.0) ? 1 : 0;
+    int tailkey = 0;
+    if (h->storage == GF_MIXED_F32_R12 && h->tail_theta > 0.0)
+        tailkey = (h->n_tail == 0) ? 1 : (h->n_tail >= h->n_active ? 2 : 3);
     GraphCache &g = h->graph;
     if (!(g.exec && g.key_upd == upd && g.key_n == n && g.key_W == h->W && g.key_tail == tailkey)) {
         g.clear();
@@ -528,8 +546,8 @@ void gf_destroy(gf_handle h) {
     if (!h->ev_pending.empty()) (void)hipStreamSynchronize(h->stream);
     h->graph.clear();
     for (auto &p : h->ev_pending) {
-        (void)hipEventDestroy(p.first);
-        (void)hipEventDestroy(p.second);
+        (void)hipEventDestroy(p.e0);
+        (void)hipEventDestroy(p.e1);
     }
     for (auto e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->hstat) (void)hipHostFree(h->hstat);
@@ -630,6 +648,8 @@ int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes) {
         if (I.g_off >= 0) HIPCHK(h, gfl::set_identity(st, h->ws, I.g_off, (int32_t)I.Vh, h->stream));
     if (h->hres) (void)hipHostFree(h->hres);
     HIPCHK(h, hipHostMalloc(reinterpret_cast<void **>(&h->hres), sizeof(double) * 4 * h->nunits, hipHostMallocDefault));
+    h->n_active = h->nunits;
+    h->n_tail = (h->tail_theta >= 1e300) ? h->nunits : 0;
     h->bound = true;
     rc = build_tiles(h, default_W(h));
     if (rc) {
@@ -936,8 +956,10 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
     const int st = st_code(h->storage);
     const int ctd = h->storage == GF_MIXED_F32_R12 ? 0 : 1;
     const bool was_timing = h->timing;
-    const double save_sum = h->t_sum_ms;
-    const int64_t save_cnt = h->t_count;
+    rc = drain_timing(h);
+    if (rc) return rc;
+    const double save_sum[2] = {h->t_sum_ms[0], h->t_sum_ms[1]};
+    const int64_t save_cnt[2] = {h->t_count[0], h->t_count[1]};
     HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_active), 1, h->nunits, h->stream));
     int bestW = h->W;
     double best = 1e300;
@@ -951,8 +973,8 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
         rc = drain_timing(h);
         if (rc) return rc;
         h->timing = true;
-        h->t_sum_ms = 0.0;
-        h->t_count = 0;
+        h->t_sum_ms[0] = h->t_sum_ms[1] = 0.0;
+        h->t_count[0] = h->t_count[1] = 0;
         for (int r = 0; r < reps; ++r) {
             rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false);
             if (rc) return rc;
@@ -960,14 +982,17 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
         rc = drain_timing(h);
         if (rc) return rc;
         h->timing = was_timing;
-        const double ms = h->t_count ? h->t_sum_ms / h->t_count : 1e300;
+        const int64_t cnt = h->t_count[0] + h->t_count[1];
+        const double ms = cnt ? (h->t_sum_ms[0] + h->t_sum_ms[1]) / cnt : 1e300;
         if (ms < best) {
             best = ms;
             bestW = W;
         }
     }
-    h->t_sum_ms = save_sum;
-    h->t_count = save_cnt;
+    for (int v = 0; v < 2; ++v) {
+        h->t_sum_ms[v] = save_sum[v];
+        h->t_count[v] = save_cnt[v];
+    }
     rc = build_tiles(h, bestW);
     if (rc) return rc;
     if (lanes_per_site) *lanes_per_site = bestW;
@@ -980,17 +1005,28 @@ int gf_set_timing(gf_handle h, int enable) {
     int rc = drain_timing(h);
     if (rc) return rc;
     h->timing = enable != 0;
-    h->t_sum_ms = 0.0;
-    h->t_count = 0;
+    h->t_sum_ms[0] = h->t_sum_ms[1] = 0.0;
+    h->t_count[0] = h->t_count[1] = 0;
     return GF_OK;
 }
 
-int gf_kernel_time(gf_handle h, int64_t *launches, double *mean_ms) {
+int gf_kernel_time(gf_handle h, int which, int64_t *launches, double *mean_ms) {
     if (!h) return GF_E_INVALID;
+    if (which < 0 || which > 2) return fail(h, GF_E_INVALID, "which must be 0, 1 or 2");
     int rc = drain_timing(h);
     if (rc) return rc;
-    if (launches) *launches = h->t_count;
-    if (mean_ms) *mean_ms = h->t_count ? h->t_sum_ms / (double)h->t_count : 0.0;
+    int64_t n = 0;
+    double ms = 0.0;
+    if (which == 0 || which == 1) {
+        n += h->t_count[0];
+        ms += h->t_sum_ms[0];
+    }
+    if (which == 0 || which == 2) {
+        n += h->t_count[1];
+        ms += h->t_sum_ms[1];
+    }
+    if (launches) *launches = n;
+    if (mean_ms) *mean_ms = n ? ms / (double)n : 0.0;
     return GF_OK;
 }
 

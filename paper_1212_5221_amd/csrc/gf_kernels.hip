@@ -188,20 +188,23 @@ __global__ __launch_bounds__(MBLOCK) void k_finalize(const gfs::UnitDev *units, 
 __global__ __launch_bounds__(MBLOCK) void k_decide(int nunits, const double *res, int32_t *active, int32_t *fp64,
                                                    double tol, double tail, int32_t *status) {
     __shared__ double sh[4];
-    double cnt = 0.0, bad = 0.0;
+    double cnt = 0.0, bad = 0.0, n64 = 0.0;
     for (int u = threadIdx.x; u < nunits; u += MBLOCK) {
         const double F = res[4 * u], th = res[4 * u + 1];
         const bool fin = isfinite(F) && isfinite(th);
         if (!fin) bad += 1.0;
         if (active[u] && th < tol) active[u] = 0;
-        fp64[u] = (th < tail) ? 1 : 0;
+        if (tail > 0.0) fp64[u] = (th < tail || tail >= 1e300) ? 1 : 0;
         cnt += active[u] ? 1.0 : 0.0;
+        n64 += (active[u] && fp64[u]) ? 1.0 : 0.0;
     }
     const double c = block_sum(cnt, sh);
     const double b = block_sum(bad, sh);
+    const double d = block_sum(n64, sh);
     if (threadIdx.x == 0) {
-        status[0] = (int32_t)c;
-        status[1] = (int32_t)b;
+        status[0] = (int32_t)c;  // active units
+        status[1] = (int32_t)b;  // units with a non-finite F or theta
+        status[2] = (int32_t)d;  // active units in the FP64 tail
     }
 }
 

@@ -85,7 +85,7 @@ def load():
     L.gf_set_launch.argtypes = [vp, ci, ci]
     L.gf_autotune.argtypes = [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)]
     L.gf_set_timing.argtypes = [vp, ci]
-    L.gf_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), dp]
+    L.gf_kernel_time.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_int64), dp]
     L.gf_set_graph.argtypes = [vp, ci]
     _lib = L
     return L
@@ -248,10 +248,12 @@ class GaugeFixer:
     def set_timing(self, enable=True):
         self._check(self.lib.gf_set_timing(self._h, 1 if enable else 0))
 
-    def kernel_time(self):
+    def kernel_time(self, which="all"):
+        """(launches, mean ms) of the timed half-sweeps: which = all | fp32 | fp64 update"""
+        w = {"all": 0, "fp32": 1, "fp64": 2}[which]
         n = ctypes.c_int64()
         ms = ctypes.c_double()
-        self._check(self.lib.gf_kernel_time(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        self._check(self.lib.gf_kernel_time(self._h, w, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
 
     def set_graph(self, enable=True):
