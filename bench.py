@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison runs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (scale for rocprof byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the gauge-fixing path is not sharded across GPUs); "
@@ -107,6 +109,16 @@ def main():
 
     import torch
     from paper_1212_5221_amd import gf, inputs as I
+
+    if args.calibrate_copy:
+        n = 1 << 30
+        x = torch.empty(n // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}))
+        return
 
     dev = torch.device("cuda:0")
     V = int(np.prod(DIMS))

@@ -20,7 +20,7 @@ namespace {
 
 struct InstHost {
     int32_t n[4];
-    int64_t V, Vh;
+    int64_t V, Vh, Vp;  // sites, half, half rounded up to 16
     int32_t unit0, nunits;
     int64_t links_off, g_off;
 };
@@ -177,13 +177,13 @@ void plan_layout(gf_ctx *h) {
     int unit = 0;
     for (auto &I : h->inst) {
         I.links_off = (int64_t)off;
-        off += align256((size_t)8 * nch * I.Vh * 16);
+        off += align256((size_t)8 * nch * I.Vp * 16);
         I.unit0 = unit;
         I.nunits = (h->gauge == GF_COULOMB) ? I.n[0] : 1;
         unit += I.nunits;
         if (h->gauge == GF_COULOMB) {
             I.g_off = (int64_t)off;
-            off += align256((size_t)2 * nch * I.Vh * 16);
+            off += align256((size_t)2 * nch * I.Vp * 16);
         } else {
             I.g_off = -1;
         }
@@ -254,7 +254,7 @@ gfs::InstDev inst_dev(const InstHost &I) {
     d.Vh = (int32_t)I.Vh;
     d.unit0 = I.unit0;
     d.nunits = I.nunits;
-    d.pad = 0;
+    d.Vp = (int32_t)I.Vp;
     d.links_off = I.links_off;
     d.g_off = I.g_off;
     return d;
@@ -386,8 +386,8 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing) {
 int launch_reunit_all(gf_ctx *h) {
     const int st = st_code(h->storage);
     for (auto &I : h->inst) {
-        HIPCHK(h, gfl::reunit(st, h->ws, I.links_off, 8, (int32_t)I.Vh, h->cur));
-        if (I.g_off >= 0) HIPCHK(h, gfl::reunit(st, h->ws, I.g_off, 2, (int32_t)I.Vh, h->cur));
+        HIPCHK(h, gfl::reunit(st, h->ws, I.links_off, 8, (int32_t)I.Vh, (int32_t)I.Vp, h->cur));
+        if (I.g_off >= 0) HIPCHK(h, gfl::reunit(st, h->ws, I.g_off, 2, (int32_t)I.Vh, (int32_t)I.Vp, h->cur));
     }
     return GF_OK;
 }
@@ -439,7 +439,7 @@ int coulomb_finish(gf_ctx *h) {
     for (auto &I : h->inst) {
         const gfs::InstDev d = inst_dev(I);
         HIPCHK(h, gfl::coulomb_fix(st, h->ws, d, h->cur));
-        HIPCHK(h, gfl::set_identity(st, h->ws, I.g_off, (int32_t)I.Vh, h->cur));
+        HIPCHK(h, gfl::set_identity(st, h->ws, I.g_off, (int32_t)I.Vh, (int32_t)I.Vp, h->cur));
     }
     return GF_OK;
 }
@@ -568,11 +568,12 @@ int gf_add_instance(gf_handle h, const int32_t dims[4], int32_t *inst) {
             return fail(h, GF_E_DIMS, "extent %d of dimension %d is not even and >= 2", dims[k], k);
         V *= dims[k];
     }
-    if (V / 2 >= ((int64_t)1 << 31)) return fail(h, GF_E_DIMS, "lattice too large (%lld sites)", (long long)V);
+    if (V / 2 >= ((int64_t)1 << 28)) return fail(h, GF_E_DIMS, "lattice too large (%lld sites)", (long long)V);
     InstHost I;
     for (int k = 0; k < 4; ++k) I.n[k] = dims[k];
     I.V = V;
     I.Vh = V / 2;
+    I.Vp = (I.Vh + 15) / 16 * 16;
     I.unit0 = I.nunits = 0;
     I.links_off = I.g_off = 0;
     h->inst.push_back(I);
@@ -645,7 +646,7 @@ int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes) {
     HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_sweeps), 0, h->nunits, h->stream));
     const int st = st_code(h->storage);
     for (auto &I : h->inst)
-        if (I.g_off >= 0) HIPCHK(h, gfl::set_identity(st, h->ws, I.g_off, (int32_t)I.Vh, h->stream));
+        if (I.g_off >= 0) HIPCHK(h, gfl::set_identity(st, h->ws, I.g_off, (int32_t)I.Vh, (int32_t)I.Vp, h->stream));
     if (h->hres) (void)hipHostFree(h->hres);
     HIPCHK(h, hipHostMalloc(reinterpret_cast<void **>(&h->hres), sizeof(double) * 4 * h->nunits, hipHostMallocDefault));
     h->n_active = h->nunits;

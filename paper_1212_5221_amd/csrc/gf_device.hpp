@@ -147,11 +147,24 @@ __device__ __forceinline__ Q4<T> qmul(const Q4<T> &a, const Q4<T> &b) {
 
 // ---------------------------------------------------------------- storage
 // Link storage (per instance, parity-split structure of arrays):
-//   plane (p, mu) holds NCH chunks, chunk c is an array of Vh 16-byte vectors;
-//   the vector of half-site h of chunk c sits at plane + c*Vh + h.
+//   plane (p, mu) holds Vp = Vh rounded up to 16 sites of NCH 16-byte
+//   vectors each, in blocks of 16 sites (see site_vec).
 // F32R12: 3 float4 chunks = rows 0,1 as (re,im) pairs.
 // F64R12: 6 double2 chunks = the 6 complex entries of rows 0,1.
 // F64R18: 9 double2 chunks = all 9 complex entries.
+// Sites are grouped in blocks of 16: chunk c of half-site h is the 16-byte
+// vector at base + ((h / 16) NCH + c) 16 + h % 16.  A wavefront of 64
+// consecutive sites reads 4 contiguous 256-byte segments per chunk, and one
+// address per link serves all chunks (immediate offsets c * 256 bytes).
+template <int NCH, typename V>
+__device__ __forceinline__ const V *site_vec(const V *base, uint32_t h) {
+    return base + (size_t)(h >> 4) * (NCH * 16) + (h & 15u);
+}
+template <int NCH, typename V>
+__device__ __forceinline__ V *site_vec(V *base, uint32_t h) {
+    return base + (size_t)(h >> 4) * (NCH * 16) + (h & 15u);
+}
+
 template <int ST>
 struct Store;
 
@@ -161,9 +174,10 @@ struct Store<gfs::ST_F32R12> {
     typedef float4 V;
     static constexpr int NR = 12, NCH = 3, ROWS = 2;
     __device__ static __forceinline__ void load(const V *__restrict__ base, int64_t Vh, int64_t h, S r[NR]) {
+        const V *sv = site_vec<NCH>(base, (uint32_t)h);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            V v = base[c * Vh + h];
+            V v = sv[16 * c];
             r[4 * c] = v.x;
             r[4 * c + 1] = v.y;
             r[4 * c + 2] = v.z;
@@ -171,8 +185,9 @@ struct Store<gfs::ST_F32R12> {
         }
     }
     __device__ static __forceinline__ void store(V *__restrict__ base, int64_t Vh, int64_t h, const S r[NR]) {
+        V *sv = site_vec<NCH>(base, (uint32_t)h);
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) base[c * Vh + h] = make_float4(r[4 * c], r[4 * c + 1], r[4 * c + 2], r[4 * c + 3]);
+        for (int c = 0; c < NCH; ++c) sv[16 * c] = make_float4(r[4 * c], r[4 * c + 1], r[4 * c + 2], r[4 * c + 3]);
     }
 };
 
@@ -182,16 +197,18 @@ struct Store<gfs::ST_F64R12> {
     typedef double2 V;
     static constexpr int NR = 12, NCH = 6, ROWS = 2;
     __device__ static __forceinline__ void load(const V *__restrict__ base, int64_t Vh, int64_t h, S r[NR]) {
+        const V *sv = site_vec<NCH>(base, (uint32_t)h);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            V v = base[c * Vh + h];
+            V v = sv[16 * c];
             r[2 * c] = v.x;
             r[2 * c + 1] = v.y;
         }
     }
     __device__ static __forceinline__ void store(V *__restrict__ base, int64_t Vh, int64_t h, const S r[NR]) {
+        V *sv = site_vec<NCH>(base, (uint32_t)h);
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) base[c * Vh + h] = make_double2(r[2 * c], r[2 * c + 1]);
+        for (int c = 0; c < NCH; ++c) sv[16 * c] = make_double2(r[2 * c], r[2 * c + 1]);
     }
 };
 
@@ -201,16 +218,18 @@ struct Store<gfs::ST_F64R18> {
     typedef double2 V;
     static constexpr int NR = 18, NCH = 9, ROWS = 3;
     __device__ static __forceinline__ void load(const V *__restrict__ base, int64_t Vh, int64_t h, S r[NR]) {
+        const V *sv = site_vec<NCH>(base, (uint32_t)h);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            V v = base[c * Vh + h];
+            V v = sv[16 * c];
             r[2 * c] = v.x;
             r[2 * c + 1] = v.y;
         }
     }
     __device__ static __forceinline__ void store(V *__restrict__ base, int64_t Vh, int64_t h, const S r[NR]) {
+        V *sv = site_vec<NCH>(base, (uint32_t)h);
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) base[c * Vh + h] = make_double2(r[2 * c], r[2 * c + 1]);
+        for (int c = 0; c < NCH; ++c) sv[16 * c] = make_double2(r[2 * c], r[2 * c + 1]);
     }
 };
 
@@ -242,13 +261,13 @@ __device__ __forceinline__ void compress(const M3<T> &m, typename Store<ST>::S *
 template <int ST>
 __device__ __forceinline__ typename Store<ST>::V *plane_ptr(char *ws, const gfs::InstDev &I, int p, int mu) {
     typedef typename Store<ST>::V V;
-    return reinterpret_cast<V *>(ws + I.links_off) + (int64_t)((p * 4 + mu) * Store<ST>::NCH) * I.Vh;
+    return reinterpret_cast<V *>(ws + I.links_off) + (int64_t)((p * 4 + mu) * Store<ST>::NCH) * I.Vp;
 }
 
 template <int ST>
 __device__ __forceinline__ typename Store<ST>::V *gacc_ptr(char *ws, const gfs::InstDev &I, int p) {
     typedef typename Store<ST>::V V;
-    return reinterpret_cast<V *>(ws + I.g_off) + (int64_t)(p * Store<ST>::NCH) * I.Vh;
+    return reinterpret_cast<V *>(ws + I.g_off) + (int64_t)(p * Store<ST>::NCH) * I.Vp;
 }
 
 // ---------------------------------------------------------------- geometry

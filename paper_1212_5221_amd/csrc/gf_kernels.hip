@@ -251,12 +251,12 @@ __device__ __forceinline__ void reproject(M3<double> &m) {
 // reproject `count` vectors-of-links: every (plane, site) of the given
 // storage region [base, base + nplanes planes of Vh sites)
 template <int ST>
-__global__ __launch_bounds__(MBLOCK) void k_reunit(char *ws, int64_t off, int32_t nplanes, int32_t Vh) {
+__global__ __launch_bounds__(MBLOCK) void k_reunit(char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp) {
     typedef Store<ST> SD;
     const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
     if (idx >= (int64_t)nplanes * Vh) return;
     const int32_t pl = (int32_t)(idx / Vh), h = (int32_t)(idx - (int64_t)pl * Vh);
-    typename SD::V *base = reinterpret_cast<typename SD::V *>(ws + off) + (int64_t)pl * SD::NCH * Vh;
+    typename SD::V *base = reinterpret_cast<typename SD::V *>(ws + off) + (int64_t)pl * SD::NCH * Vp;
     typename SD::S r[SD::NR];
     SD::load(base, Vh, h, r);
     M3<double> m;
@@ -268,12 +268,12 @@ __global__ __launch_bounds__(MBLOCK) void k_reunit(char *ws, int64_t off, int32_
 
 // identity into the Coulomb accumulator (2 parity planes)
 template <int ST>
-__global__ __launch_bounds__(MBLOCK) void k_set_identity(char *ws, int64_t off, int32_t Vh) {
+__global__ __launch_bounds__(MBLOCK) void k_set_identity(char *ws, int64_t off, int32_t Vh, int32_t Vp) {
     typedef Store<ST> SD;
     const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
     if (idx >= 2 * (int64_t)Vh) return;
     const int32_t pl = (int32_t)(idx / Vh), h = (int32_t)(idx - (int64_t)pl * Vh);
-    typename SD::V *base = reinterpret_cast<typename SD::V *>(ws + off) + (int64_t)pl * SD::NCH * Vh;
+    typename SD::V *base = reinterpret_cast<typename SD::V *>(ws + off) + (int64_t)pl * SD::NCH * Vp;
     M3<double> m;
     m3_identity(m);
     typename SD::S r[SD::NR];
@@ -419,25 +419,25 @@ hipError_t fill_i32(int32_t *p, int32_t v, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, hipStream_t s) {
+hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp, hipStream_t s) {
     const int64_t n = (int64_t)nplanes * Vh;
     if (st == gfs::ST_F64R18)
-        k_reunit<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh);
+        k_reunit<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh, Vp);
     else if (st == gfs::ST_F64R12)
-        k_reunit<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh);
+        k_reunit<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh, Vp);
     else
-        k_reunit<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh);
+        k_reunit<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh, Vp);
     return hipGetLastError();
 }
 
-hipError_t set_identity(int st, char *ws, int64_t off, int32_t Vh, hipStream_t s) {
+hipError_t set_identity(int st, char *ws, int64_t off, int32_t Vh, int32_t Vp, hipStream_t s) {
     const int64_t n = 2 * (int64_t)Vh;
     if (st == gfs::ST_F64R18)
-        k_set_identity<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, off, Vh);
+        k_set_identity<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, off, Vh, Vp);
     else if (st == gfs::ST_F64R12)
-        k_set_identity<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, Vh);
+        k_set_identity<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, Vh, Vp);
     else
-        k_set_identity<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, Vh);
+        k_set_identity<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, Vh, Vp);
     return hipGetLastError();
 }
 

@@ -25,8 +25,8 @@ hipError_t decide(int nunits, const double *res, int32_t *active, int32_t *fp64,
 hipError_t count_sweep(int ninst, const gfs::InstDev *inst, const int32_t *active, int32_t *sweeps_done,
                        uint64_t *sweep_ix, hipStream_t s);
 hipError_t fill_i32(int32_t *p, int32_t v, int n, hipStream_t s);
-hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, hipStream_t s);
-hipError_t set_identity(int st, char *ws, int64_t off, int32_t Vh, hipStream_t s);
+hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp, hipStream_t s);
+hipError_t set_identity(int st, char *ws, int64_t off, int32_t Vh, int32_t Vp, hipStream_t s);
 hipError_t convert_in(int st, char *ws, const gfs::InstDev &I, const double *src, int64_t s0, int64_t ns,
                       hipStream_t s);
 hipError_t convert_out(int st, const char *ws, const gfs::InstDev &I, double *dst, int64_t s0, int64_t ns, int reunit,

@@ -16,7 +16,7 @@ struct InstDev {
     int32_t Vh;        // half the number of sites
     int32_t unit0;     // first unit of this instance
     int32_t nunits;    // 1 (Landau, MAG) or Nt (Coulomb)
-    int32_t pad;
+    int32_t Vp;        // Vh rounded up to a multiple of 16 (plane stride in sites)
     int64_t links_off; // byte offset of the link planes in the workspace
     int64_t g_off;     // byte offset of the Coulomb accumulator (or -1)
 };

@@ -454,7 +454,13 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
         }
     }
 
-    // ---- Step 2: apply G to this wave's links and store
+    // ---- Step 2: apply G to this wave's links and store.
+    // The empty asm makes the stored rows opaque, so the compiler rebuilds
+    // the third rows here instead of keeping all expanded links live.
+#pragma unroll
+    for (int q = 0; q < LPW; ++q)
+#pragma unroll
+        for (int c = 0; c < SD::NR; ++c) asm volatile("" : "+v"(r[q][c]));
 #pragma unroll
     for (int q = 0; q < LPW; ++q) {
         const int l = wv * LPW + q;

@@ -1,0 +1,131 @@
+"""Simulated annealing (Sec. 2.3) on the GPU against the oracle.
+
+FP64 storage: the GPU and the oracle draw the same Philox4x64-10 numbers
+(keyed by seed and instance, counter by sweep index, site, subgroup, draw),
+so the annealed configurations agree to rounding: the MAG sampler has no
+rejection step; the Landau sampler's accept/reject decisions could in
+principle flip on a rounding difference, which these small runs do not hit.
+Mixed storage cannot follow the FP64 chain (FP32 rounding changes the
+samples), so at full size (32^4 MAG, the annealing workload) it is checked by
+properties and by one overrelaxation half-sweep recomputed by the oracle on
+sampled sites of the annealed state.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1212_5221_amd import inputs as I
+from tests.test_gpu_parity import fixer, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("gauge", ["mag", "landau", "coulomb"])
+@pytest.mark.parametrize("storage", ["f64r18", "f64r12"])
+def test_anneal_matches_oracle(gauge, storage):
+    dims = (4, 4, 6, 4)
+    say("anneal", gauge, storage)
+    U = I.smooth(dims, 0.7, 4001)
+    ref = U.copy()
+    V = int(np.prod(dims))
+    G = O.identity_field(V) if gauge == "coulomb" else None
+    ctr = O.anneal(ref, dims, gauge, 1.5, 0.01, 12, nmicro=3, seed=4002, instance=0, sweep_counter=0, G=G)
+    if gauge == "coulomb":
+        O.coulomb_fix_u0(ref, dims, G)
+    fx = fixer([dims], gauge, storage)
+    fx.upload(0, U)
+    fx.set_anneal(1.5, 0.01, 12, nmicro=3, seed=4002)
+    st, done = fx.sweep("anneal")
+    assert fx.get_sweep_index(0) == ctr == 12 * 4
+    out = fx.download(0)
+    err = np.max(np.abs(out - ref))
+    say("max |gpu - oracle| after annealing", err)
+    assert err < 1e-10
+    # then overrelaxation to theta < 1e-12 on both sides
+    r = O.run(ref, dims, gauge, "or", omega=1.7, max_sweeps=3000, tol=1e-12, check_every=5, sweep_counter=ctr)
+    fx.set_overrelax(1.7)
+    st, done = fx.sweep("or", max_sweeps=3000, tol=1e-12, check_every=5)
+    out = fx.download(0)
+    fx.close()
+    assert st == 0 and r.status == 0
+    np.testing.assert_array_equal(done, r.sweeps_done.astype(np.int32))
+    assert np.max(np.abs(out - ref)) < 1e-9
+
+
+def test_anneal_resume_is_bit_identical():
+    # checkpoint/resume: the random streams depend only on (seed, instance,
+    # sweep index, site), so two halves with the sweep index carried over
+    # give the same chain as one run
+    dims = (4, 4, 4, 4)
+    say("anneal resume")
+    U = I.smooth(dims, 0.7, 4003)
+    a = fixer([dims], "mag", "f64r18")
+    a.upload(0, U)
+    a.set_seed(9)
+    a.set_temperature(0.8)
+    for k in range(6):
+        a.sweep("heatbath", max_sweeps=1, tol=0.0)
+    full = a.download(0)
+    a.close()
+    b = fixer([dims], "mag", "f64r18")
+    b.upload(0, U)
+    b.set_seed(9)
+    b.set_temperature(0.8)
+    for k in range(3):
+        b.sweep("heatbath", max_sweeps=1, tol=0.0)
+    idx = b.get_sweep_index(0)
+    mid = b.download(0)
+    b.close()
+    c = fixer([dims], "mag", "f64r18")
+    c.upload(0, mid)
+    c.set_seed(9)
+    c.set_temperature(0.8)
+    c.set_sweep_index(0, idx)
+    for k in range(3):
+        c.sweep("heatbath", max_sweeps=1, tol=0.0)
+    np.testing.assert_array_equal(c.download(0), full)
+    c.close()
+
+
+def test_c4_mag_anneal_full_size():
+    # 32^4, eps = 0.7: T 1.5 -> 0.01 over 3000 heatbath sweeps (+3 micro),
+    # then overrelaxation omega = 1.7 to theta < 1e-12, mixed storage
+    dims = (32, 32, 32, 32)
+    say("C4 full size")
+    U = I.smooth(dims, 0.7, 4001)
+    plaq = O.plaquette(U, dims)
+    fx = fixer([dims], "mag", "mixed", reunit_every=100, tail_theta=1e-9)
+    fx.upload(0, U)
+    fx.set_anneal(1.5, 0.01, 3000, nmicro=3, seed=4002)
+    st, done = fx.sweep("anneal")
+    assert fx.get_sweep_index(0) == 12000
+    F_sa, th_sa = fx.measure(0)
+    annealed = fx.download(0)
+    # one OR half-sweep on the annealed state vs the oracle on sampled sites
+    from tests.test_gpu_fullsize import _site_links
+    from tests._su import coords
+    fx.set_overrelax(1.7)
+    fx.halfsweep("or", 0)
+    one = fx.download(0)
+    ref = annealed.copy()  # the download is the FP32 state (row 2 rebuilt in FP64)
+    rng = np.random.default_rng(6)
+    sites = []
+    while len(sites) < 128:
+        s = int(rng.integers(0, U.shape[0]))
+        if sum(coords(dims, s)) % 2 == 0:
+            sites.append(s)
+    O.update_sites(ref, dims, "mag", "or", sites, omega=1.7)
+    err = max(float(np.max(np.abs(one[q, m] - ref[q, m]))) for s in sites for (q, m) in _site_links(U, dims, s))
+    say("annealed: F", F_sa, "theta", th_sa, "OR half-sweep max err", err)
+    assert err < 3e-5
+    st, done = fx.sweep("or", max_sweeps=100000, tol=1e-12, check_every=10)
+    fx.reunitarise()
+    F, th = fx.measure(0)
+    out = fx.download(0, reunitarise=True)
+    fx.close()
+    say("after OR: status", st, "sweeps", done, "F", F, "theta", th)
+    assert st == 0
+    assert F > F_sa
+    assert abs(O.plaquette(out, dims) - plaq) < 1e-6
+    Fo, tho = O.measure(out, dims, "mag")
+    assert abs(Fo - F) < 1e-9 and tho < 1.5e-12

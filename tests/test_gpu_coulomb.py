@@ -1,0 +1,76 @@
+"""Coulomb gauge at full size: 64^3 x 256 (256 independent time-slices of 64^3,
+about 13 GB of FP32 12-real links) fixed in one batched launch with
+per-time-slice stopping, mixed storage, omega = 1.7, theta < 1e-12.
+
+Checked on sampled time-slices {0, 85, 170, 255}: one half-sweep recomputed
+site by site by the oracle from the same FP32-rounded input slice (the
+update of a time-slice depends on that slice only), and after the full fix
+the oracle's per-slice F_t and theta_t of the downloaded slice.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1212_5221_amd import inputs as I
+from tests.test_gpu_parity import f32_round, fixer, say
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (256, 64, 64, 64)
+SLICES = (0, 85, 170, 255)
+SLAB = 16
+
+
+def _upload(fx):
+    for t0 in range(0, DIMS[0], SLAB):
+        fx.upload(0, I.smooth(DIMS, 0.5, 3001, t0=t0, nt=SLAB), t0=t0, nt=SLAB)
+
+
+def test_c3_coulomb_full_size():
+    say("C3: generating and uploading 64^3 x 256 in slabs of", SLAB)
+    fx = fixer([DIMS], "coulomb", "mixed", reunit_every=100, tail_theta=1e-9)
+    _upload(fx)
+    fx.set_overrelax(1.7)
+    fx.autotune(reps=1)
+    _upload(fx)  # autotuning ran real sweeps: start again from the input
+    say("C3: one half-sweep, sampled sites")
+    fx.halfsweep("or", 0)
+    d1 = (1,) + DIMS[1:]
+    Vs = DIMS[1] * DIMS[2] * DIMS[3]
+    rng = np.random.default_rng(7)
+    from tests._su import coords, site_index
+    for t in SLICES:
+        got = fx.download(0, t0=t, nt=1)
+        ref = f32_round(I.smooth(DIMS, 0.5, 3001, t0=t, nt=1))
+        sites = []
+        while len(sites) < 64:
+            s = int(rng.integers(0, Vs))
+            if sum(coords(d1, s)[1:]) % 2 == 0:
+                sites.append(s)
+        O.update_sites(ref, d1, "coulomb", "or", sites, omega=1.7, G=O.identity_field(Vs))
+        err = 0.0
+        for s in sites:
+            _, x, y, z = coords(d1, s)
+            for mu, c in ((1, (0, x, y, z)), (2, (0, x, y, z)), (3, (0, x, y, z))):
+                err = max(err, float(np.max(np.abs(got[s, mu] - ref[s, mu]))))
+                b = list(c)
+                b[mu] = (b[mu] - 1) % d1[mu]
+                q = site_index(d1, *b)
+                err = max(err, float(np.max(np.abs(got[q, mu] - ref[q, mu]))))
+        say("slice", t, "max |gpu - oracle|", err)
+        assert err < 3e-5
+    say("C3: full fix")
+    _upload(fx)
+    st, done = fx.sweep("or", max_sweeps=50000, tol=1e-12, check_every=10)
+    fx.reunitarise()
+    Ft, tht = fx.measure_timeslices(0)
+    say("status", st, "sweeps min/max", done.min(), done.max(), "theta max", tht.max())
+    assert st == 0
+    assert np.all(tht < 1.5e-12)
+    assert len(set(done.tolist())) > 1  # time-slices stop on their own
+    for t in SLICES:
+        got = fx.download(0, t0=t, nt=1, reunitarise=True)
+        Fo, tho = O.measure_slices(got, d1)
+        say("slice", t, "F gpu", Ft[t], "oracle", Fo[0], "theta", tho[0])
+        assert abs(Fo[0] - Ft[t]) < 1e-9 and tho[0] < 1.5e-12
+    fx.close()
