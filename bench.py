@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (scale for rocprof byte counters)")
+    ap.add_argument("--profile-sweeps", type=int, default=0,
+                    help="only run this many OR sweeps of the workload (for profiler counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the gauge-fixing path is not sharded across GPUs); "
@@ -118,6 +120,22 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}))
+        return
+    if args.profile_sweeps:
+        # a fixed number of OR sweeps of seed 2001 in the benchmark's launch
+        # configuration (for profiler counter runs)
+        fx = make_fixer(gf, "mixed")
+        fx.upload(0, I.smooth(DIMS, EPS, SEEDS[0]))
+        lanes, _ = fx.autotune(reps=1)
+        fx.upload(0, I.smooth(DIMS, EPS, SEEDS[0]))
+        fx.set_timing(True)
+        fx.sweep("or", max_sweeps=args.profile_sweeps, tol=0.0, check_every=args.profile_sweeps)
+        n, ms = fx.kernel_time("fp32")
+        fx.close()
+        bpl = BYTES_PER_SITE["mixed"] * int(np.prod(DIMS)) / 2
+        print(json.dumps({"profile_sweeps": args.profile_sweeps, "waves_per_site_group": lanes, "launches": n,
+                          "mean_launch_ms": ms, "bytes_per_launch": bpl,
+                          "achieved_GBs": bpl / (ms * 1e-3) / 1e9 if ms > 0 else None}))
         return
 
     dev = torch.device("cuda:0")

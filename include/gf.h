@@ -178,16 +178,21 @@ int gf_reunitarise(gf_handle h);
 int gf_get_sweep_index(gf_handle h, int32_t inst, uint64_t *index);
 int gf_set_sweep_index(gf_handle h, int32_t inst, uint64_t index);
 
-/* Kernel configuration.  lanes_per_site: lanes of a wavefront sharing one
-   site (1, 2 or 4; 0 = library default); block: threads per workgroup (64,
-   128, 256 or 512; 0 = default).  GF_E_INVALID for an unavailable variant. */
-int gf_set_launch(gf_handle h, int lanes_per_site, int block);
+/* Kernel configuration.  waves_per_site: wavefronts sharing a group of 64
+   sites, each holding 8/waves_per_site (Coulomb 6/waves_per_site) of the
+   adjacent links, with the partial sums exchanged through LDS (the
+   eight-threads-per-site idea of Sec. 4.3 at wavefront granularity): 1, 2 or
+   4 (Coulomb 1 or 2); 0 = library default.  Applies to the FP32-update and
+   the FP64-update kernels where the variant exists.  block: threads per
+   workgroup, 256 (or 0).  GF_E_INVALID for an unavailable variant. */
+int gf_set_launch(gf_handle h, int waves_per_site, int block);
 
-/* Time the available launch variants of the OR half-sweep on the bound
-   configuration (each variant runs `reps` real OR sweeps, which advance the
-   fixing) and keep the fastest.  *lanes_per_site and *block (may be NULL)
-   receive the choice. */
-int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block);
+/* Time the available variants of the OR half-sweep on the bound
+   configuration, separately for each compute precision the configuration
+   uses (each variant runs `reps` real OR sweeps, which advance the fixing),
+   and keep the fastest.  *waves_per_site (of the precision doing most
+   sweeps) and *block (may be NULL) receive the choice. */
+int gf_autotune(gf_handle h, int reps, int *waves_per_site, int *block);
 
 /* Kernel timing: while enabled, every half-sweep launch is bracketed by HIP
    events on the handle's stream (HIP graphs are not used meanwhile).

@@ -62,16 +62,18 @@ struct gf_ctx {
     size_t ws_bytes = 0;
 
     // workspace layout (byte offsets)
-    size_t off_inst = 0, off_unit = 0, off_tiles = 0, off_mtiles = 0, off_partial = 0, off_res = 0;
+    size_t off_inst = 0, off_unit = 0, off_tiles[2] = {0, 0}, off_mtiles = 0, off_partial = 0, off_res = 0;
     size_t off_active = 0, off_fp64 = 0, off_sweeps = 0, off_sweepix = 0, off_status = 0, off_stage = 0;
     size_t stage_bytes = 0, need_bytes = 0;
     int nunits = 0, nmtiles = 0;
     int64_t max_tiles = 0;
     std::vector<gfs::UnitDev> units;
 
-    // launch configuration
-    int W = 1;
-    int ntiles = 0;  // sweep tiles for the current W
+    // launch configuration per compute precision of the update (0 FP32, 1 FP64):
+    // wavefronts per group of 64 sites and the matching sweep tile tables
+    int W[2] = {1, 1};
+    int ntiles[2] = {0, 0};
+    int force_ctd = -1;  // autotuning: time one precision only
 
     // host readback (pinned)
     int32_t *hstat = nullptr;
@@ -93,6 +95,7 @@ struct gf_ctx {
 
     // from the last check: active units, of which in the FP64 tail
     int n_active = 0, n_tail = 0;
+    hipEvent_t chk_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -160,11 +163,6 @@ int upd_code(int update) {
     }
 }
 
-int default_W(const gf_ctx *h) {
-    (void)h;
-    return 1;
-}
-
 template <typename T>
 T *wsp(gf_ctx *h, size_t off) {
     return reinterpret_cast<T *>(h->ws + off);
@@ -221,8 +219,10 @@ void plan_layout(gf_ctx *h) {
     off += align256(sizeof(gfs::InstDev) * h->inst.size());
     h->off_unit = off;
     off += align256(sizeof(gfs::UnitDev) * h->nunits);
-    h->off_tiles = off;
-    off += align256(sizeof(gfs::Tile) * (size_t)h->max_tiles);
+    for (int v = 0; v < 2; ++v) {
+        h->off_tiles[v] = off;
+        off += align256(sizeof(gfs::Tile) * (size_t)h->max_tiles);
+    }
     h->off_mtiles = off;
     off += align256(sizeof(gfs::MTile) * (size_t)h->nmtiles);
     h->off_partial = off;
@@ -260,19 +260,29 @@ gfs::InstDev inst_dev(const InstHost &I) {
     return d;
 }
 
-int build_tiles(gf_ctx *h, int W) {
+int build_tiles(gf_ctx *h, int ctd, int W) {
     const int spb = gfl::SWEEP_THREADS / W;
     std::vector<gfs::Tile> t;
     for (int u = 0; u < h->nunits; ++u)
         for (int32_t j = 0; j < h->units[u].n; j += spb) t.push_back({u, j});
     if ((int64_t)t.size() > h->max_tiles) return fail(h, GF_E_INVALID, "tile table overflow");
-    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_tiles, t.data(), sizeof(gfs::Tile) * t.size(), hipMemcpyHostToDevice,
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_tiles[ctd], t.data(), sizeof(gfs::Tile) * t.size(), hipMemcpyHostToDevice,
                              h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    h->ntiles = (int)t.size();
-    h->W = W;
+    h->ntiles[ctd] = (int)t.size();
+    h->W[ctd] = W;
     h->graph.clear();
     return GF_OK;
+}
+
+// default wavefronts per site group: FP32 update 1, FP64 update the largest
+// available of 4, 2, 1 (fewer links per wavefront, more waves in flight)
+int default_W_for(const gf_ctx *h, int ctd) {
+    const int st = st_code(h->storage);
+    if (ctd == 0) return 1;
+    for (int W = 4; W >= 1; W /= 2)
+        if (gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, 1, W)) return W;
+    return 1;
 }
 
 int check_bound(gf_ctx *h) {
@@ -287,12 +297,12 @@ int check_unbound(gf_ctx *h) {
     return GF_OK;
 }
 
-gfs::SweepArgs sweep_args(gf_ctx *h, int parity, int fp64_select, double T) {
+gfs::SweepArgs sweep_args(gf_ctx *h, int parity, int fp64_select, double T, int ctd) {
     gfs::SweepArgs a;
     a.ws = h->ws;
     a.inst = wsp<gfs::InstDev>(h, h->off_inst);
     a.unit = wsp<gfs::UnitDev>(h, h->off_unit);
-    a.tiles = wsp<gfs::Tile>(h, h->off_tiles);
+    a.tiles = wsp<gfs::Tile>(h, h->off_tiles[ctd]);
     a.active = wsp<int32_t>(h, h->off_active);
     a.fp64 = wsp<int32_t>(h, h->off_fp64);
     a.sweep_ix = wsp<uint64_t>(h, h->off_sweepix);
@@ -341,7 +351,9 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing) {
         int ctd, sel;
     } launches[2];
     int nl = 0;
-    if (!mixed || hb) {
+    if (h->force_ctd >= 0) {
+        launches[nl++] = {h->force_ctd, -1};
+    } else if (!mixed || hb) {
         launches[nl++] = {1, -1};
     } else if (h->tail_theta > 0.0) {
         // only the variants some active unit needs (counts of the last check)
@@ -357,10 +369,11 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing) {
         launches[nl++] = {0, -1};
     }
     for (int k = 0; k < nl; ++k) {
-        gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, st, launches[k].ctd, h->W);
+        const int ctd = launches[k].ctd;
+        gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, st, ctd, h->W[ctd]);
         if (!fn) return fail(h, GF_E_INVALID, "no kernel variant for gauge %d update %d storage %d W %d", h->gauge, upd,
-                             h->storage, h->W);
-        gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T);
+                             h->storage, h->W[ctd]);
+        gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T, ctd);
         const bool tm = h->timing && !capturing;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tm) {
@@ -369,7 +382,7 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing) {
             if (!e0 || !e1) return fail(h, GF_E_HIP, "hipEventCreate failed");
             HIPCHK(h, hipEventRecord(e0, h->cur));
         }
-        fn<<<dim3((unsigned)h->ntiles), dim3(gfl::SWEEP_THREADS), 0, h->cur>>>(a);
+        fn<<<dim3((unsigned)h->ntiles[ctd]), dim3(gfl::SWEEP_THREADS), 0, h->cur>>>(a);
         HIPCHK(h, hipGetLastError());
         if (tm) {
             HIPCHK(h, hipEventRecord(e1, h->cur));
@@ -463,7 +476,8 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
     if (h->storage == GF_MIXED_F32_R12 && h->tail_theta > 0.0)
         tailkey = (h->n_tail == 0) ? 1 : (h->n_tail >= h->n_active ? 2 : 3);
     GraphCache &g = h->graph;
-    if (!(g.exec && g.key_upd == upd && g.key_n == n && g.key_W == h->W && g.key_tail == tailkey)) {
+    const int wkey = h->W[0] * 16 + h->W[1];
+    if (!(g.exec && g.key_upd == upd && g.key_n == n && g.key_W == wkey && g.key_tail == tailkey)) {
         g.clear();
         if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
         HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
@@ -485,7 +499,7 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
         HIPCHK(h, hipGraphInstantiate(&g.exec, gr, nullptr, nullptr, 0));
         g.key_upd = upd;
         g.key_n = n;
-        g.key_W = h->W;
+        g.key_W = wkey;
         g.key_tail = tailkey;
     }
     HIPCHK(h, hipGraphLaunch(g.exec, h->stream));
@@ -531,7 +545,7 @@ int gf_create(gf_handle *out, int hip_device, void *hip_stream) {
     h->dev = hip_device;
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     h->cur = h->stream;
-    e = hipHostMalloc(reinterpret_cast<void **>(&h->hstat), 64, hipHostMallocDefault);
+    e = hipHostMalloc(reinterpret_cast<void **>(&h->hstat), 16 * sizeof(int32_t), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete h;
         return fail(nullptr, GF_E_HIP, "hipHostMalloc: %s", hipGetErrorString(e));
@@ -553,6 +567,8 @@ void gf_destroy(gf_handle h) {
     if (h->hstat) (void)hipHostFree(h->hstat);
     if (h->hres) (void)hipHostFree(h->hres);
     if (h->cap) (void)hipStreamDestroy(h->cap);
+    for (auto e : h->chk_ev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
 }
 
@@ -652,7 +668,8 @@ int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes) {
     h->n_active = h->nunits;
     h->n_tail = (h->tail_theta >= 1e300) ? h->nunits : 0;
     h->bound = true;
-    rc = build_tiles(h, default_W(h));
+    rc = build_tiles(h, 0, default_W_for(h, 0));
+    if (rc == GF_OK) rc = build_tiles(h, 1, default_W_for(h, 1));
     if (rc) {
         h->bound = false;
         return rc;
@@ -783,31 +800,67 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
     if (upd < 0) return fail(h, GF_E_INVALID, "bad update type %d", update);
     if (max_sweeps < 0) return fail(h, GF_E_INVALID, "max_sweeps < 0");
     if (check_every < 1) check_every = 1;
+    // Checks at k = 0, c, 2c, ... measure theta and stop units on the device.
+    // The next chunk of sweeps is enqueued before the host reads a check's
+    // status: sweep kernels skip stopped units, so a chunk queued after the
+    // last unit stopped changes nothing, and the GPU never idles while the
+    // host waits.  Kernel variants (FP32 / FP64 update) follow the status of
+    // the check before, which keeps the schedule deterministic.
+    for (int e = 0; e < 2; ++e)
+        if (!h->chk_ev[e]) HIPCHK(h, hipEventCreateWithFlags(&h->chk_ev[e], hipEventDisableTiming));
+    struct Pend {
+        int slot, k;
+    };
+    Pend pend[2];
+    int npend = 0, slot = 0;
+    auto enqueue_check = [&](int kk) -> int {
+        int r = launch_measure(h, 0);
+        if (r) return r;
+        r = launch_decide(h, theta_tol);
+        if (r) return r;
+        HIPCHK(h, hipMemcpyAsync(h->hstat + 4 * slot, h->ws + h->off_status, 3 * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipEventRecord(h->chk_ev[slot], h->stream));
+        pend[npend++] = {slot, kk};
+        slot ^= 1;
+        return GF_OK;
+    };
     int status = GF_OK;
     int k = 0;
+    bool stopped = false;
+    rc = enqueue_check(0);
+    if (rc) return rc;
     for (;;) {
-        if (k % check_every == 0) {
-            rc = launch_measure(h, 0);
-            if (rc) return rc;
-            rc = launch_decide(h, theta_tol);
-            if (rc) return rc;
-            rc = read_status(h);
-            if (rc) return rc;
-            if (h->hstat[1] != 0) {
+        if (npend == 2 || (k >= max_sweeps && npend > 0)) {
+            const Pend c = pend[0];
+            pend[0] = pend[1];
+            --npend;
+            HIPCHK(h, hipEventSynchronize(h->chk_ev[c.slot]));
+            const int32_t *st = h->hstat + 4 * c.slot;
+            if (st[1] != 0) {
+                HIPCHK(h, hipStreamSynchronize(h->stream));
                 (void)fetch_sweeps_done(h, sweeps_done);
-                return fail(h, GF_E_NONFINITE, "F or theta not finite in %d unit(s) after %d sweeps", h->hstat[1], k);
+                return fail(h, GF_E_NONFINITE, "F or theta not finite in %d unit(s) after %d sweeps", st[1], c.k);
             }
-            if (h->hstat[0] == 0) break;
+            h->n_active = st[0];
+            h->n_tail = st[2];
+            if (st[0] == 0) {
+                stopped = true;
+                break;
+            }
+            continue;
         }
-        if (k >= max_sweeps) {
-            status = GF_NOT_CONVERGED;
-            break;
-        }
+        if (k >= max_sweeps) break;
         const int n = std::min(check_every - k % check_every, max_sweeps - k);
         rc = run_sweeps(h, upd, n, k, n == check_every);
         if (rc) return rc;
         k += n;
+        if (k % check_every == 0) {
+            rc = enqueue_check(k);
+            if (rc) return rc;
+        }
     }
+    if (!stopped) status = GF_NOT_CONVERGED;
     rc = coulomb_finish(h);
     if (rc) return rc;
     rc = drain_timing(h);
@@ -939,15 +992,32 @@ int gf_set_sweep_index(gf_handle h, int32_t inst, uint64_t index) {
     return GF_OK;
 }
 
+// compute precisions of the update this configuration uses (bit 0 FP32, bit 1 FP64)
+static int used_precisions(const gf_ctx *h) {
+    if (h->storage != GF_MIXED_F32_R12) return 2;
+    if (h->tail_theta <= 0.0) return 1;
+    if (h->tail_theta >= 1e300) return 2;
+    return 3;
+}
+
+// the precision doing most of the sweeps
+static int dominant_ctd(const gf_ctx *h) { return (used_precisions(h) & 1) ? 0 : 1; }
+
 int gf_set_launch(gf_handle h, int lanes_per_site, int block) {
     int rc = check_bound(h);
     if (rc) return rc;
-    const int W = lanes_per_site == 0 ? default_W(h) : lanes_per_site;
     if (block != 0 && block != gfl::SWEEP_THREADS) return fail(h, GF_E_INVALID, "block %d not available", block);
     const int st = st_code(h->storage);
-    if (!gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, h->storage == GF_MIXED_F32_R12 ? 0 : 1, W))
-        return fail(h, GF_E_INVALID, "no variant with %d wavefronts per site group", W);
-    return build_tiles(h, W);
+    int set = 0;
+    for (int ctd = 0; ctd < 2; ++ctd) {
+        const int W = lanes_per_site == 0 ? default_W_for(h, ctd) : lanes_per_site;
+        if (!gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, ctd, W)) continue;
+        rc = build_tiles(h, ctd, W);
+        if (rc) return rc;
+        ++set;
+    }
+    if (!set) return fail(h, GF_E_INVALID, "no variant with %d wavefronts per site group", lanes_per_site);
+    return GF_OK;
 }
 
 int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
@@ -955,48 +1025,53 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
     if (rc) return rc;
     if (reps < 1) reps = 1;
     const int st = st_code(h->storage);
-    const int ctd = h->storage == GF_MIXED_F32_R12 ? 0 : 1;
     const bool was_timing = h->timing;
     rc = drain_timing(h);
     if (rc) return rc;
     const double save_sum[2] = {h->t_sum_ms[0], h->t_sum_ms[1]};
     const int64_t save_cnt[2] = {h->t_count[0], h->t_count[1]};
     HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_active), 1, h->nunits, h->stream));
-    int bestW = h->W;
-    double best = 1e300;
-    for (int W = 1; W <= 8; W *= 2) {
-        if (!gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, ctd, W)) continue;
-        rc = build_tiles(h, W);
-        if (rc) return rc;
-        // warm-up sweep, then timed sweeps
-        rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false);
-        if (rc) return rc;
-        rc = drain_timing(h);
-        if (rc) return rc;
-        h->timing = true;
-        h->t_sum_ms[0] = h->t_sum_ms[1] = 0.0;
-        h->t_count[0] = h->t_count[1] = 0;
-        for (int r = 0; r < reps; ++r) {
-            rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false);
-            if (rc) return rc;
+    const int used = used_precisions(h);
+    for (int ctd = 0; ctd < 2; ++ctd) {
+        if (!(used & (1 << ctd))) continue;
+        int bestW = h->W[ctd];
+        double best = 1e300;
+        h->force_ctd = ctd;
+        for (int W = 1; W <= 8; W *= 2) {
+            if (!gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, ctd, W)) continue;
+            rc = build_tiles(h, ctd, W);
+            // warm-up sweep, then timed sweeps (real OR sweeps: they advance the fixing)
+            if (rc == GF_OK) rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false);
+            if (rc == GF_OK) rc = drain_timing(h);
+            if (rc) {
+                h->force_ctd = -1;
+                return rc;
+            }
+            h->timing = true;
+            h->t_sum_ms[0] = h->t_sum_ms[1] = 0.0;
+            h->t_count[0] = h->t_count[1] = 0;
+            for (int r = 0; r < reps && rc == GF_OK; ++r) rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false);
+            if (rc == GF_OK) rc = drain_timing(h);
+            h->timing = was_timing;
+            if (rc) {
+                h->force_ctd = -1;
+                return rc;
+            }
+            const double ms = h->t_count[ctd] ? h->t_sum_ms[ctd] / h->t_count[ctd] : 1e300;
+            if (ms < best) {
+                best = ms;
+                bestW = W;
+            }
         }
-        rc = drain_timing(h);
+        h->force_ctd = -1;
+        rc = build_tiles(h, ctd, bestW);
         if (rc) return rc;
-        h->timing = was_timing;
-        const int64_t cnt = h->t_count[0] + h->t_count[1];
-        const double ms = cnt ? (h->t_sum_ms[0] + h->t_sum_ms[1]) / cnt : 1e300;
-        if (ms < best) {
-            best = ms;
-            bestW = W;
-        }
     }
     for (int v = 0; v < 2; ++v) {
         h->t_sum_ms[v] = save_sum[v];
         h->t_count[v] = save_cnt[v];
     }
-    rc = build_tiles(h, bestW);
-    if (rc) return rc;
-    if (lanes_per_site) *lanes_per_site = bestW;
+    if (lanes_per_site) *lanes_per_site = h->W[dominant_ctd(h)];
     if (block) *block = gfl::SWEEP_THREADS;
     return GF_OK;
 }

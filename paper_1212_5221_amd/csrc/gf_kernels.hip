@@ -66,7 +66,7 @@ __device__ __forceinline__ cx<double> det3(const M3<double> &m) {
 }
 
 // Per site (both parities): F contribution of the forward links, theta of
-// the site; optional |1 - det U| of the forward links.  Partials per tile.
+// the site; optional |1 - det U| of the four forward links.  Partials per tile.
 template <int GAUGE, int ST>
 __global__ __launch_bounds__(MBLOCK) void k_measure(gfs::MeasureArgs a) {
     typedef Store<ST> SD;
@@ -93,12 +93,6 @@ __global__ __launch_bounds__(MBLOCK) void k_measure(gfs::MeasureArgs a) {
         M3<double> m;
         SD::load(plane_ptr<ST>(a.ws, I, p, mu), I.Vh, h, r);
         expand<ST, double>(r, m);
-        if (a.with_unitarity) {
-            const cx<double> d = det3(m);
-            const double e = sqrt((1.0 - d.re) * (1.0 - d.re) + d.im * d.im);
-            us += e;
-            um = fmax(um, e);
-        }
         if constexpr (GAUGE == gfs::MAG) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) F += cnorm2(m.e[i][i]);
@@ -139,6 +133,19 @@ __global__ __launch_bounds__(MBLOCK) void k_measure(gfs::MeasureArgs a) {
     } else {
         th = delta_norm2(K);
     }
+    if (a.with_unitarity) {
+        // |1 - det U| of the forward links of every direction (temporal ones too)
+        for (int mu = 0; mu < 4; ++mu) {
+            typename SD::S r[SD::NR];
+            M3<double> m;
+            SD::load(plane_ptr<ST>(a.ws, I, p, mu), I.Vh, h, r);
+            expand<ST, double>(r, m);
+            const cx<double> d = det3(m);
+            const double e = sqrt((1.0 - d.re) * (1.0 - d.re) + d.im * d.im);
+            us += e;
+            um = fmax(um, e);
+        }
+    }
     if (!valid) F = th = us = um = 0.0;
     const double bF = block_sum(F, sh);
     const double bT = block_sum(th, sh);
@@ -177,7 +184,7 @@ __global__ __launch_bounds__(MBLOCK) void k_finalize(const gfs::UnitDev *units, 
         const double V = 2.0 * (double)U.n;
         out[4 * blockIdx.x] = bF / (3.0 * ndir * V);
         out[4 * blockIdx.x + 1] = bT / (3.0 * V);
-        out[4 * blockIdx.x + 2] = bU / (ndir * V);
+        out[4 * blockIdx.x + 2] = bU / (4.0 * V);
         out[4 * blockIdx.x + 3] = bM;
     }
 }
