@@ -36,7 +36,7 @@ OMEGA = 1.7
 TOL = 1e-12
 CHECK = 10
 REUNIT = 100
-TAIL = 1e-9          # FP64 update once theta < 1e-9
+TAIL = 0.0           # FP64 update arithmetic below this theta (0: FP32 update throughout; Step 2 is FP64)
 MAX_SWEEPS = 50000
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"mixed": 768, "f64r12": 1536, "f64r18": 2304}  # 8 links loaded + stored
@@ -145,7 +145,7 @@ def main():
     torch.cuda.synchronize()
 
     fx = make_fixer(gf, "mixed")
-    lanes, _ = fx.autotune(reps=2)
+    lanes, _ = fx.autotune(reps=5)
     log("autotune: waves per site group", lanes)
     for w in range(args.warmup):
         one_fix(fx, inputs[w % len(SEEDS)])

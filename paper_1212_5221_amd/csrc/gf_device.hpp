@@ -116,6 +116,24 @@ __device__ __forceinline__ void apply_right_dag3(const M3<T> &a, const M3<T> &b,
         }
 }
 
+// reprojection to SU(3) (Sec. 4.5): normalise row 0, Gram-Schmidt row 1,
+// row 2 = (row0 x row1)^*
+template <typename T>
+__device__ __forceinline__ void reproject(M3<T> &m) {
+    const T n0 = T(1) / sqrt(cnorm2(m.e[0][0]) + cnorm2(m.e[0][1]) + cnorm2(m.e[0][2]));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m.e[0][k] = cmk(m.e[0][k].re * n0, m.e[0][k].im * n0);
+    cx<T> pr = cmk(T(0), T(0));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pr = cadd(pr, cmulc(m.e[1][k], m.e[0][k]));  // conj(row0) . row1
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m.e[1][k] = csub(m.e[1][k], cmul(pr, m.e[0][k]));
+    const T n1 = T(1) / sqrt(cnorm2(m.e[1][0]) + cnorm2(m.e[1][1]) + cnorm2(m.e[1][2]));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m.e[1][k] = cmk(m.e[1][k].re * n1, m.e[1][k].im * n1);
+    m3_row2(m);
+}
+
 // SU(2) element as 4 reals (g0, g1, g2, g3): [[g0 + i g3, g2 + i g1], [-g2 + i g1, g0 - i g3]]
 template <typename T>
 struct Q4 {

@@ -237,24 +237,6 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int n) {
 }
 
 // ---------------------------------------------------------------- reprojection
-// normalise row 0, Gram-Schmidt row 1, row 2 = (row0 x row1)^*  (in FP64)
-__device__ __forceinline__ void reproject(M3<double> &m) {
-    double n0 = cnorm2(m.e[0][0]) + cnorm2(m.e[0][1]) + cnorm2(m.e[0][2]);
-    n0 = 1.0 / sqrt(n0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) m.e[0][k] = cmk(m.e[0][k].re * n0, m.e[0][k].im * n0);
-    cx<double> pr = cmk(0.0, 0.0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) pr = cadd(pr, cmulc(m.e[1][k], m.e[0][k]));  // conj(row0) . row1
-#pragma unroll
-    for (int k = 0; k < 3; ++k) m.e[1][k] = csub(m.e[1][k], cmul(pr, m.e[0][k]));
-    double n1 = cnorm2(m.e[1][0]) + cnorm2(m.e[1][1]) + cnorm2(m.e[1][2]);
-    n1 = 1.0 / sqrt(n1);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) m.e[1][k] = cmk(m.e[1][k].re * n1, m.e[1][k].im * n1);
-    m3_row2(m);
-}
-
 // reproject `count` vectors-of-links: every (plane, site) of the given
 // storage region [base, base + nplanes planes of Vh sites)
 template <int ST>

@@ -19,6 +19,8 @@
 // the explicit form).
 #pragma once
 
+#include <type_traits>
+
 #include "gf_device.hpp"
 
 namespace gfd {
@@ -461,18 +463,28 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
     for (int q = 0; q < LPW; ++q)
 #pragma unroll
         for (int c = 0; c < SD::NR; ++c) asm volatile("" : "+v"(r[q][c]));
+    // FP32 storage: G is applied in FP64, and a G built in FP32 is first
+    // reprojected to SU(3) in FP64.  An exactly unitary G keeps the links on
+    // their gauge orbit, so the only loss is the rounding of the stored links.
+    typedef typename std::conditional<ST == gfs::ST_F32R12, double, CT>::type AT;
+    M3<AT> Ga;
+#pragma unroll
+    for (int i2 = 0; i2 < 3; ++i2)
+#pragma unroll
+        for (int j2 = 0; j2 < 3; ++j2) Ga.e[i2][j2] = cmk<AT>(AT(G.e[i2][j2].re), AT(G.e[i2][j2].im));
+    if constexpr (!std::is_same<AT, CT>::value) reproject(Ga);
 #pragma unroll
     for (int q = 0; q < LPW; ++q) {
         const int l = wv * LPW + q;
         const bool fw = l < NDIR;
         const int mu = MU0 + (fw ? l : l - NDIR);
-        M3<CT> m, o;
-        expand<ST, CT>(r[q], m);
+        M3<AT> m, o;
+        expand<ST, AT>(r[q], m);
         if (fw)
-            apply_left(G, m, o, SD::ROWS);
+            apply_left(Ga, m, o, SD::ROWS);
         else
-            apply_right_dag(G, m, o, SD::ROWS);
-        compress<ST, CT>(o, r[q]);
+            apply_right_dag(Ga, m, o, SD::ROWS);
+        compress<ST, AT>(o, r[q]);
         if (valid) SD::store(plane_ptr<ST>(a.ws, I, fw ? p : 1 - p, mu), I.Vh, lh[q], r[q]);
     }
 
@@ -482,10 +494,10 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
         V *gp = gacc_ptr<ST>(a.ws, I, p);
         S gr[SD::NR];
         SD::load(gp, I.Vh, h, gr);
-        M3<CT> m, o;
-        expand<ST, CT>(gr, m);
-        apply_left(G, m, o, SD::ROWS);
-        compress<ST, CT>(o, gr);
+        M3<AT> m, o;
+        expand<ST, AT>(gr, m);
+        apply_left(Ga, m, o, SD::ROWS);
+        compress<ST, AT>(o, gr);
         if (valid) SD::store(gp, I.Vh, h, gr);
       }
     }
