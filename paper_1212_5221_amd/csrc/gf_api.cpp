@@ -2,6 +2,7 @@
 // carving, instance and unit tables, the Alg. 1 driver with per-unit
 // stopping, annealing schedules, HIP-graph capture of the sweep loop,
 // kernel timing and the autotuner.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -89,6 +90,7 @@ struct gf_ctx {
     std::vector<Pending> ev_pending;
     double t_sum_ms[2] = {0.0, 0.0};
     int64_t t_count[2] = {0, 0};
+    double t_min_ms[2] = {1e300, 1e300};
 
     bool use_graph = true;
     GraphCache graph;
@@ -297,7 +299,7 @@ int check_unbound(gf_ctx *h) {
     return GF_OK;
 }
 
-gfs::SweepArgs sweep_args(gf_ctx *h, int parity, int fp64_select, double T, int ctd) {
+gfs::SweepArgs sweep_args(gf_ctx *h, int parity, int fp64_select, double T, int ctd, int sweep_off) {
     gfs::SweepArgs a;
     a.ws = h->ws;
     a.inst = wsp<gfs::InstDev>(h, h->off_inst);
@@ -308,6 +310,8 @@ gfs::SweepArgs sweep_args(gf_ctx *h, int parity, int fp64_select, double T, int 
     a.sweep_ix = wsp<uint64_t>(h, h->off_sweepix);
     a.parity = parity;
     a.fp64_select = fp64_select;
+    a.sweep_off = sweep_off;
+    a.pad = 0;
     a.omega = h->omega;
     a.T = T;
     a.p_sr = h->p_sr;
@@ -334,6 +338,7 @@ int drain_timing(gf_ctx *h) {
         HIPCHK(h, hipEventElapsedTime(&ms, p.e0, p.e1));
         h->t_sum_ms[p.ctd] += ms;
         h->t_count[p.ctd] += 1;
+        h->t_min_ms[p.ctd] = std::min(h->t_min_ms[p.ctd], (double)ms);
         h->ev_pool.push_back(p.e0);
         h->ev_pool.push_back(p.e1);
     }
@@ -342,7 +347,7 @@ int drain_timing(gf_ctx *h) {
 }
 
 // one half-sweep of update `upd` (gfs code) at temperature T on all active units
-int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing) {
+int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sweep_off) {
     const int st = st_code(h->storage);
     const bool mixed = (h->storage == GF_MIXED_F32_R12);
     const bool hb = (upd == gfs::UPD_HEATBATH || upd == gfs::UPD_SR);
@@ -373,24 +378,23 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing) {
         gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, st, ctd, h->W[ctd]);
         if (!fn) return fail(h, GF_E_INVALID, "no kernel variant for gauge %d update %d storage %d W %d", h->gauge, upd,
                              h->storage, h->W[ctd]);
-        gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T, ctd);
+        gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T, ctd, sweep_off);
         const bool tm = h->timing && !capturing;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tm) {
-            e0 = take_event(h);
-            e1 = take_event(h);
+            // the launch itself records its start and stop events
+            hipEvent_t e0 = take_event(h), e1 = take_event(h);
             if (!e0 || !e1) return fail(h, GF_E_HIP, "hipEventCreate failed");
-            HIPCHK(h, hipEventRecord(e0, h->cur));
-        }
-        fn<<<dim3((unsigned)h->ntiles[ctd]), dim3(gfl::SWEEP_THREADS), 0, h->cur>>>(a);
-        HIPCHK(h, hipGetLastError());
-        if (tm) {
-            HIPCHK(h, hipEventRecord(e1, h->cur));
+            void *args[] = {&a};
+            HIPCHK(h, hipExtLaunchKernel(reinterpret_cast<const void *>(fn), dim3((unsigned)h->ntiles[ctd]),
+                                         dim3(gfl::SWEEP_THREADS), args, 0, h->cur, e0, e1, 0));
             h->ev_pending.push_back({e0, e1, launches[k].ctd});
             if (h->ev_pending.size() > 4096) {
                 int rc = drain_timing(h);
                 if (rc) return rc;
             }
+        } else {
+            fn<<<dim3((unsigned)h->ntiles[ctd]), dim3(gfl::SWEEP_THREADS), 0, h->cur>>>(a);
+            HIPCHK(h, hipGetLastError());
         }
     }
     return GF_OK;
@@ -406,18 +410,27 @@ int launch_reunit_all(gf_ctx *h) {
 }
 
 // one full sweep (both parities) + bookkeeping [+ reprojection]
-int launch_sweep(gf_ctx *h, int upd, double T, bool reunit_now, bool capturing) {
+// one full sweep (both parities) [+ reprojection]; sweep_off is the sweep's
+// position in its chunk (random counter offset), counted by count_chunk
+int launch_sweep(gf_ctx *h, int upd, double T, bool reunit_now, bool capturing, int sweep_off) {
     for (int p = 0; p < 2; ++p) {
-        int rc = launch_half(h, upd, p, T, capturing);
+        int rc = launch_half(h, upd, p, T, capturing, sweep_off);
         if (rc) return rc;
     }
-    HIPCHK(h, gfl::count_sweep((int)h->inst.size(), wsp<gfs::InstDev>(h, h->off_inst), wsp<int32_t>(h, h->off_active),
-                               wsp<int32_t>(h, h->off_sweeps), wsp<uint64_t>(h, h->off_sweepix), h->cur));
     if (reunit_now) return launch_reunit_all(h);
     return GF_OK;
 }
 
-int launch_measure(gf_ctx *h, int with_unitarity) {
+// after a chunk of n sweeps: sweeps_done and the random-stream index
+int count_chunk(gf_ctx *h, int n) {
+    HIPCHK(h, gfl::count_sweep((int)h->inst.size(), wsp<gfs::InstDev>(h, h->off_inst), wsp<int32_t>(h, h->off_active),
+                               wsp<int32_t>(h, h->off_sweeps), wsp<uint64_t>(h, h->off_sweepix), n, h->cur));
+    return GF_OK;
+}
+
+// F / theta of every unit; with decide, also the stopping decision (one
+// finalize kernel whose last block decides)
+int launch_measure(gf_ctx *h, int with_unitarity, bool decide = false, double tol = 0.0) {
     gfs::MeasureArgs a;
     a.ws = h->ws;
     a.inst = wsp<gfs::InstDev>(h, h->off_inst);
@@ -426,25 +439,19 @@ int launch_measure(gf_ctx *h, int with_unitarity) {
     a.partial = wsp<double>(h, h->off_partial);
     a.with_unitarity = with_unitarity;
     HIPCHK(h, gfl::measure(h->gauge, st_code(h->storage), (unsigned)h->nmtiles, h->cur, a));
-    HIPCHK(h, gfl::finalize(h->nunits, wsp<gfs::UnitDev>(h, h->off_unit), wsp<double>(h, h->off_partial), ndir(h),
-                            wsp<double>(h, h->off_res), h->cur));
-    return GF_OK;
-}
-
-int launch_decide(gf_ctx *h, double tol) {
+    if (!decide) {
+        HIPCHK(h, gfl::finalize(h->nunits, wsp<gfs::UnitDev>(h, h->off_unit), wsp<double>(h, h->off_partial),
+                                ndir(h), wsp<double>(h, h->off_res), h->cur));
+        return GF_OK;
+    }
     const double tail = (h->storage == GF_MIXED_F32_R12) ? h->tail_theta : 0.0;
-    HIPCHK(h, gfl::decide(h->nunits, wsp<double>(h, h->off_res), wsp<int32_t>(h, h->off_active),
-                          wsp<int32_t>(h, h->off_fp64), tol, tail, wsp<int32_t>(h, h->off_status), h->cur));
+    HIPCHK(h, gfl::finalize_decide(h->nunits, wsp<gfs::UnitDev>(h, h->off_unit), wsp<double>(h, h->off_partial),
+                                   ndir(h), wsp<double>(h, h->off_res), wsp<int32_t>(h, h->off_active),
+                                   wsp<int32_t>(h, h->off_fp64), tol, tail, wsp<int32_t>(h, h->off_status),
+                                   wsp<uint32_t>(h, h->off_status + 16), h->cur));
     return GF_OK;
 }
 
-int read_status(gf_ctx *h) {
-    HIPCHK(h, hipMemcpyAsync(h->hstat, h->ws + h->off_status, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    h->n_active = h->hstat[0];
-    h->n_tail = h->hstat[2];
-    return GF_OK;
-}
 
 int coulomb_finish(gf_ctx *h) {
     if (h->gauge != GF_COULOMB) return GF_OK;
@@ -467,10 +474,10 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
     if (!graph_ok) {
         for (int i = 0; i < n; ++i) {
             const bool rn = (R > 0) && ((k0 + i + 1) % R == 0);
-            int rc = launch_sweep(h, upd, h->T, rn, false);
+            int rc = launch_sweep(h, upd, h->T, rn, false, i);
             if (rc) return rc;
         }
-        return GF_OK;
+        return count_chunk(h, n);
     }
     int tailkey = 0;
     if (h->storage == GF_MIXED_F32_R12 && h->tail_theta > 0.0)
@@ -485,8 +492,9 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
         int rc = GF_OK;
         for (int i = 0; i < n && rc == GF_OK; ++i) {
             const bool rn = (R > 0) && ((i + 1) % R == 0);
-            rc = launch_sweep(h, upd, h->T, rn, true);
+            rc = launch_sweep(h, upd, h->T, rn, true, i);
         }
+        if (rc == GF_OK) rc = count_chunk(h, n);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(h->cap, &gr);
         h->cur = h->stream;
@@ -660,6 +668,7 @@ int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes) {
     // 1e300 or more means "always FP64"
     HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_fp64), h->tail_theta >= 1e300 ? 1 : 0, h->nunits, h->stream));
     HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_sweeps), 0, h->nunits, h->stream));
+    HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_status), 0, 8, h->stream));  // status + finalize counter
     const int st = st_code(h->storage);
     for (auto &I : h->inst)
         if (I.g_off >= 0) HIPCHK(h, gfl::set_identity(st, h->ws, I.g_off, (int32_t)I.Vh, (int32_t)I.Vp, h->stream));
@@ -780,12 +789,14 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
         for (int k = 0; k < h->sa_steps; ++k) {
             const double T =
                 (h->sa_steps > 1) ? h->sa_T0 + (h->sa_T1 - h->sa_T0) * (double)k / (double)(h->sa_steps - 1) : h->sa_T0;
-            rc = launch_sweep(h, gfs::UPD_HEATBATH, T, false, false);
+            rc = launch_sweep(h, gfs::UPD_HEATBATH, T, false, false, 0);
             if (rc) return rc;
             for (int m = 0; m < h->sa_micro; ++m) {
-                rc = launch_sweep(h, gfs::UPD_MICRO, T, false, false);
+                rc = launch_sweep(h, gfs::UPD_MICRO, T, false, false, 1 + m);
                 if (rc) return rc;
             }
+            rc = count_chunk(h, 1 + h->sa_micro);
+            if (rc) return rc;
         }
         rc = coulomb_finish(h);
         if (rc) return rc;
@@ -814,9 +825,7 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
     Pend pend[2];
     int npend = 0, slot = 0;
     auto enqueue_check = [&](int kk) -> int {
-        int r = launch_measure(h, 0);
-        if (r) return r;
-        r = launch_decide(h, theta_tol);
+        int r = launch_measure(h, 0, true, theta_tol);
         if (r) return r;
         HIPCHK(h, hipMemcpyAsync(h->hstat + 4 * slot, h->ws + h->off_status, 3 * sizeof(int32_t),
                                  hipMemcpyDeviceToHost, h->stream));
@@ -879,7 +888,7 @@ int gf_halfsweep(gf_handle h, int update, int parity) {
     if (parity != 0 && parity != 1) return fail(h, GF_E_INVALID, "parity must be 0 or 1");
     HIPCHK(h, hipSetDevice(h->dev));
     HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_active), 1, h->nunits, h->stream));
-    rc = launch_half(h, upd, parity, h->T, false);
+    rc = launch_half(h, upd, parity, h->T, false, 0);
     if (rc) return rc;
     rc = drain_timing(h);
     if (rc) return rc;
@@ -1041,7 +1050,8 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
             if (!gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, ctd, W)) continue;
             rc = build_tiles(h, ctd, W);
             // warm-up sweep, then timed sweeps (real OR sweeps: they advance the fixing)
-            if (rc == GF_OK) rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false);
+            if (rc == GF_OK) rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false, 0);
+            if (rc == GF_OK) rc = count_chunk(h, 1);
             if (rc == GF_OK) rc = drain_timing(h);
             if (rc) {
                 h->force_ctd = -1;
@@ -1050,14 +1060,19 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
             h->timing = true;
             h->t_sum_ms[0] = h->t_sum_ms[1] = 0.0;
             h->t_count[0] = h->t_count[1] = 0;
-            for (int r = 0; r < reps && rc == GF_OK; ++r) rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false);
+            h->t_min_ms[0] = h->t_min_ms[1] = 1e300;
+            for (int r = 0; r < reps && rc == GF_OK; ++r) {
+                rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false, 0);
+                if (rc == GF_OK) rc = count_chunk(h, 1);
+            }
             if (rc == GF_OK) rc = drain_timing(h);
             h->timing = was_timing;
             if (rc) {
                 h->force_ctd = -1;
                 return rc;
             }
-            const double ms = h->t_count[ctd] ? h->t_sum_ms[ctd] / h->t_count[ctd] : 1e300;
+            // the fastest launch: robust against interference from other work
+            const double ms = h->t_min_ms[ctd];
             if (ms < best) {
                 best = ms;
                 bestW = W;
@@ -1083,6 +1098,7 @@ int gf_set_timing(gf_handle h, int enable) {
     h->timing = enable != 0;
     h->t_sum_ms[0] = h->t_sum_ms[1] = 0.0;
     h->t_count[0] = h->t_count[1] = 0;
+    h->t_min_ms[0] = h->t_min_ms[1] = 1e300;
     return GF_OK;
 }
 

@@ -163,11 +163,42 @@ __global__ __launch_bounds__(MBLOCK) void k_measure(gfs::MeasureArgs a) {
     }
 }
 
+// Stopping decision after a measurement (over all units): a unit stops at
+// the first check with theta < tol; counts active units, flags non-finite
+// values, sets the FP64-tail flag.
+__device__ __forceinline__ void decide_units(int nunits, const double *res, int32_t *active, int32_t *fp64, double tol,
+                                             double tail, int32_t *status, double *sh) {
+    double cnt = 0.0, bad = 0.0, n64 = 0.0;
+    for (int u = threadIdx.x; u < nunits; u += MBLOCK) {
+        const double F = __hip_atomic_load(res + 4 * u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double th = __hip_atomic_load(res + 4 * u + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool fin = isfinite(F) && isfinite(th);
+        if (!fin) bad += 1.0;
+        if (active[u] && th < tol) active[u] = 0;
+        if (tail > 0.0) fp64[u] = (th < tail || tail >= 1e300) ? 1 : 0;
+        cnt += active[u] ? 1.0 : 0.0;
+        n64 += (active[u] && fp64[u]) ? 1.0 : 0.0;
+    }
+    const double c = block_sum(cnt, sh);
+    const double b = block_sum(bad, sh);
+    const double d = block_sum(n64, sh);
+    if (threadIdx.x == 0) {
+        status[0] = (int32_t)c;  // active units
+        status[1] = (int32_t)b;  // units with a non-finite F or theta
+        status[2] = (int32_t)d;  // active units in the FP64 tail
+    }
+}
+
 // One block per unit: sum the unit's tile partials in a fixed order and
-// normalise: F = sum / (3 NDIR V_u), theta = sum / (3 V_u).
+// normalise: F = sum / (3 NDIR V_u), theta = sum / (3 V_u).  With `decide`,
+// the last block to finish (device-scope fence + counter) also takes the
+// stopping decision over all units and resets the counter.
 __global__ __launch_bounds__(MBLOCK) void k_finalize(const gfs::UnitDev *units, const double *partial, int ndir,
-                                                     double *out /* 4 per unit */) {
+                                                     double *out /* 4 per unit */, int nunits, int decide,
+                                                     int32_t *active, int32_t *fp64, double tol, double tail,
+                                                     int32_t *status, uint32_t *counter) {
     __shared__ double sh[4];
+    __shared__ int last;
     const gfs::UnitDev U = units[blockIdx.x];
     double F = 0.0, th = 0.0, us = 0.0, um = 0.0;
     for (int t = U.mtile0 + threadIdx.x; t < U.mtile1; t += MBLOCK) {
@@ -187,48 +218,34 @@ __global__ __launch_bounds__(MBLOCK) void k_finalize(const gfs::UnitDev *units, 
         out[4 * blockIdx.x + 2] = bU / (4.0 * V);
         out[4 * blockIdx.x + 3] = bM;
     }
-}
-
-// Stopping decision after a measurement (one block): a unit stops at the
-// first check with theta < tol; counts active units, flags non-finite values,
-// sets the FP64-tail flag.  status[0] = active units, status[1] = non-finite.
-__global__ __launch_bounds__(MBLOCK) void k_decide(int nunits, const double *res, int32_t *active, int32_t *fp64,
-                                                   double tol, double tail, int32_t *status) {
-    __shared__ double sh[4];
-    double cnt = 0.0, bad = 0.0, n64 = 0.0;
-    for (int u = threadIdx.x; u < nunits; u += MBLOCK) {
-        const double F = res[4 * u], th = res[4 * u + 1];
-        const bool fin = isfinite(F) && isfinite(th);
-        if (!fin) bad += 1.0;
-        if (active[u] && th < tol) active[u] = 0;
-        if (tail > 0.0) fp64[u] = (th < tail || tail >= 1e300) ? 1 : 0;
-        cnt += active[u] ? 1.0 : 0.0;
-        n64 += (active[u] && fp64[u]) ? 1.0 : 0.0;
-    }
-    const double c = block_sum(cnt, sh);
-    const double b = block_sum(bad, sh);
-    const double d = block_sum(n64, sh);
+    if (!decide) return;
     if (threadIdx.x == 0) {
-        status[0] = (int32_t)c;  // active units
-        status[1] = (int32_t)b;  // units with a non-finite F or theta
-        status[2] = (int32_t)d;  // active units in the FP64 tail
+        __threadfence();
+        const uint32_t prev = atomicAdd(counter, 1u);
+        last = (prev == (uint32_t)nunits - 1u);
     }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    decide_units(nunits, out, active, fp64, tol, tail, status, sh);
+    if (threadIdx.x == 0) *counter = 0u;
 }
 
-// After every sweep: count it for the units that took part, advance the
+// After a chunk of n sweeps (units stop only at checks, so a unit active now
+// took part in all n): count them for the active units and advance the
 // random-stream index of every instance with an active unit.
 __global__ void k_count_sweep(int ninst, const gfs::InstDev *inst, const int32_t *active, int32_t *sweeps_done,
-                              uint64_t *sweep_ix) {
+                              uint64_t *sweep_ix, int32_t n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ninst) return;
     const gfs::InstDev I = inst[i];
     int any = 0;
     for (int u = I.unit0; u < I.unit0 + I.nunits; ++u)
         if (active[u]) {
-            ++sweeps_done[u];
+            sweeps_done[u] += n;
             any = 1;
         }
-    if (any) ++sweep_ix[i];
+    if (any) sweep_ix[i] += (uint64_t)n;
 }
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int n) {
@@ -386,19 +403,22 @@ hipError_t measure(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs:
 
 hipError_t finalize(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, double *out,
                     hipStream_t s) {
-    k_finalize<<<nunits, MBLOCK, 0, s>>>(units, partial, ndir, out);
+    k_finalize<<<nunits, MBLOCK, 0, s>>>(units, partial, ndir, out, nunits, 0, nullptr, nullptr, 0.0, 0.0, nullptr,
+                                         nullptr);
     return hipGetLastError();
 }
 
-hipError_t decide(int nunits, const double *res, int32_t *active, int32_t *fp64, double tol, double tail,
-                  int32_t *status, hipStream_t s) {
-    k_decide<<<1, MBLOCK, 0, s>>>(nunits, res, active, fp64, tol, tail, status);
+hipError_t finalize_decide(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, double *out,
+                           int32_t *active, int32_t *fp64, double tol, double tail, int32_t *status,
+                           uint32_t *counter, hipStream_t s) {
+    k_finalize<<<nunits, MBLOCK, 0, s>>>(units, partial, ndir, out, nunits, 1, active, fp64, tol, tail, status,
+                                         counter);
     return hipGetLastError();
 }
 
 hipError_t count_sweep(int ninst, const gfs::InstDev *inst, const int32_t *active, int32_t *sweeps_done,
-                       uint64_t *sweep_ix, hipStream_t s) {
-    k_count_sweep<<<(ninst + 63) / 64, 64, 0, s>>>(ninst, inst, active, sweeps_done, sweep_ix);
+                       uint64_t *sweep_ix, int32_t n, hipStream_t s) {
+    k_count_sweep<<<(ninst + 63) / 64, 64, 0, s>>>(ninst, inst, active, sweeps_done, sweep_ix, n);
     return hipGetLastError();
 }
 

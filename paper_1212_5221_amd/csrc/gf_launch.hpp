@@ -20,10 +20,11 @@ constexpr int SWEEP_THREADS = 256;
 hipError_t measure(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a);
 hipError_t finalize(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, double *out,
                     hipStream_t s);
-hipError_t decide(int nunits, const double *res, int32_t *active, int32_t *fp64, double tol, double tail,
-                  int32_t *status, hipStream_t s);
+hipError_t finalize_decide(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, double *out,
+                           int32_t *active, int32_t *fp64, double tol, double tail, int32_t *status,
+                           uint32_t *counter, hipStream_t s);
 hipError_t count_sweep(int ninst, const gfs::InstDev *inst, const int32_t *active, int32_t *sweeps_done,
-                       uint64_t *sweep_ix, hipStream_t s);
+                       uint64_t *sweep_ix, int32_t n, hipStream_t s);
 hipError_t fill_i32(int32_t *p, int32_t v, int n, hipStream_t s);
 hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp, hipStream_t s);
 hipError_t set_identity(int st, char *ws, int64_t off, int32_t Vh, int32_t Vp, hipStream_t s);

@@ -55,6 +55,8 @@ struct SweepArgs {
     const uint64_t *sweep_ix; // per instance: global sweep index (random counter)
     int32_t parity;           // active parity (Coulomb: 3D parity)
     int32_t fp64_select;      // -1 all units, else only units whose flag equals it
+    int32_t sweep_off;        // random counter = sweep_ix[inst] + sweep_off (sweeps counted per chunk)
+    int32_t pad;
     double omega, T, p_sr;
     uint64_t seed;
 };

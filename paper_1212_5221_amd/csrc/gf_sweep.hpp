@@ -352,7 +352,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
     Rng rng;
     rng.k0 = a.seed;
     rng.k1 = (uint64_t)U.inst;
-    rng.sweep = a.sweep_ix[U.inst];
+    rng.sweep = a.sweep_ix[U.inst] + (uint64_t)a.sweep_off;
     rng.site = (uint64_t)natural_index(I, s);
 
     M3<CT> G;
