@@ -400,11 +400,18 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
     return GF_OK;
 }
 
-int launch_reunit_all(gf_ctx *h) {
+// reprojection of every link (and Coulomb accumulator); inside gf_sweep
+// (only_active) stopped units are skipped, so they keep the links their
+// stopping check measured
+int launch_reunit_all(gf_ctx *h, bool only_active) {
     const int st = st_code(h->storage);
+    const int32_t *act = only_active ? wsp<int32_t>(h, h->off_active) : nullptr;
     for (auto &I : h->inst) {
-        HIPCHK(h, gfl::reunit(st, h->ws, I.links_off, 8, (int32_t)I.Vh, (int32_t)I.Vp, h->cur));
-        if (I.g_off >= 0) HIPCHK(h, gfl::reunit(st, h->ws, I.g_off, 2, (int32_t)I.Vh, (int32_t)I.Vp, h->cur));
+        HIPCHK(h, gfl::reunit(st, h->ws, I.links_off, 8, (int32_t)I.Vh, (int32_t)I.Vp, act, I.unit0, I.nunits,
+                              h->cur));
+        if (I.g_off >= 0)
+            HIPCHK(h, gfl::reunit(st, h->ws, I.g_off, 2, (int32_t)I.Vh, (int32_t)I.Vp, act, I.unit0, I.nunits,
+                                  h->cur));
     }
     return GF_OK;
 }
@@ -417,7 +424,7 @@ int launch_sweep(gf_ctx *h, int upd, double T, bool reunit_now, bool capturing, 
         int rc = launch_half(h, upd, p, T, capturing, sweep_off);
         if (rc) return rc;
     }
-    if (reunit_now) return launch_reunit_all(h);
+    if (reunit_now) return launch_reunit_all(h, true);
     return GF_OK;
 }
 
@@ -971,7 +978,7 @@ int gf_reunitarise(gf_handle h) {
     int rc = check_bound(h);
     if (rc) return rc;
     HIPCHK(h, hipSetDevice(h->dev));
-    rc = launch_reunit_all(h);
+    rc = launch_reunit_all(h, false);
     if (rc) return rc;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return GF_OK;

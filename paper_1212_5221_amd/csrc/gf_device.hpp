@@ -134,6 +134,29 @@ __device__ __forceinline__ void reproject(M3<T> &m) {
     m3_row2(m);
 }
 
+// One first-order reprojection step on the two stored rows of a 12-real
+// link: the row norms and their overlap move from 1 + d, e to 1 + O(d^2),
+// O(e d), with no division or square root.  The rebuilt third row scales with
+// the product of the two row norms, so under left multiplication by a
+// unitary matrix far from the identity a norm defect of the stored rows
+// grows by a factor of about 4/3 per update; links that keep receiving large
+// updates (annealing, the first sweeps from a random gauge) would leave SU(3)
+// exponentially fast without this step.
+template <typename T>
+__device__ __forceinline__ void renormalise_rows(M3<T> &m) {
+    const T s0 = T(1.5) - T(0.5) * (cnorm2(m.e[0][0]) + cnorm2(m.e[0][1]) + cnorm2(m.e[0][2]));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m.e[0][k] = cmk(m.e[0][k].re * s0, m.e[0][k].im * s0);
+    cx<T> pr = cmk(T(0), T(0));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pr = cadd(pr, cmulc(m.e[1][k], m.e[0][k]));  // conj(row0) . row1
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m.e[1][k] = csub(m.e[1][k], cmul(pr, m.e[0][k]));
+    const T s1 = T(1.5) - T(0.5) * (cnorm2(m.e[1][0]) + cnorm2(m.e[1][1]) + cnorm2(m.e[1][2]));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m.e[1][k] = cmk(m.e[1][k].re * s1, m.e[1][k].im * s1);
+}
+
 // SU(2) element as 4 reals (g0, g1, g2, g3): [[g0 + i g3, g2 + i g1], [-g2 + i g1, g0 - i g3]]
 template <typename T>
 struct Q4 {
@@ -262,11 +285,14 @@ __device__ __forceinline__ void expand(const typename Store<ST>::S *r, M3<T> &m)
     if (ROWS == 2) m3_row2(m);
 }
 
-// the stored rows of m back to registers (rounding to the storage precision)
+// the stored rows of m back to registers (rounding to the storage precision);
+// 12-real storage first takes one first-order reprojection step
 template <int ST, typename T>
-__device__ __forceinline__ void compress(const M3<T> &m, typename Store<ST>::S *r) {
+__device__ __forceinline__ void compress(const M3<T> &m_in, typename Store<ST>::S *r) {
     typedef typename Store<ST>::S S;
     constexpr int ROWS = Store<ST>::ROWS;
+    M3<T> m = m_in;
+    if constexpr (ROWS == 2) renormalise_rows(m);
 #pragma unroll
     for (int i = 0; i < ROWS; ++i)
 #pragma unroll

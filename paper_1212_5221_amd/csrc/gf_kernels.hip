@@ -257,11 +257,14 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int n) {
 // reproject `count` vectors-of-links: every (plane, site) of the given
 // storage region [base, base + nplanes planes of Vh sites)
 template <int ST>
-__global__ __launch_bounds__(MBLOCK) void k_reunit(char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp) {
+__global__ __launch_bounds__(MBLOCK) void k_reunit(char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp,
+                                                   const int32_t *active, int32_t unit0, int32_t hper) {
     typedef Store<ST> SD;
     const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
     if (idx >= (int64_t)nplanes * Vh) return;
     const int32_t pl = (int32_t)(idx / Vh), h = (int32_t)(idx - (int64_t)pl * Vh);
+    // a stopped unit keeps the links it stopped with
+    if (active && !active[unit0 + h / hper]) return;
     typename SD::V *base = reinterpret_cast<typename SD::V *>(ws + off) + (int64_t)pl * SD::NCH * Vp;
     typename SD::S r[SD::NR];
     SD::load(base, Vh, h, r);
@@ -428,14 +431,16 @@ hipError_t fill_i32(int32_t *p, int32_t v, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp, hipStream_t s) {
+hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp, const int32_t *active,
+                  int32_t unit0, int32_t nunits, hipStream_t s) {
     const int64_t n = (int64_t)nplanes * Vh;
+    const int32_t hper = Vh / nunits;
     if (st == gfs::ST_F64R18)
-        k_reunit<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh, Vp);
+        k_reunit<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh, Vp, active, unit0, hper);
     else if (st == gfs::ST_F64R12)
-        k_reunit<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh, Vp);
+        k_reunit<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh, Vp, active, unit0, hper);
     else
-        k_reunit<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh, Vp);
+        k_reunit<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh, Vp, active, unit0, hper);
     return hipGetLastError();
 }
 

@@ -1,10 +1,13 @@
 """Simulated annealing (Sec. 2.3) on the GPU against the oracle.
 
 FP64 storage: the GPU and the oracle draw the same Philox4x64-10 numbers
-(keyed by seed and instance, counter by sweep index, site, subgroup, draw),
-so the annealed configurations agree to rounding: the MAG sampler has no
-rejection step; the Landau sampler's accept/reject decisions could in
-principle flip on a rounding difference, which these small runs do not hit.
+(keyed by seed and instance, counter by sweep index, site, subgroup, draw).
+The annealing dynamics amplify any difference by about 1e3 per annealing
+step (one heatbath and three microcanonical sweeps; the oracle against a
+1e-15-perturbed copy of itself shows the same growth, see
+tests/test_oracle_iteration.py), so GPU and oracle chains are compared over
+one annealing step, where rounding differences stay below 1e-8, and longer
+chains by invariants and convergence.
 Mixed storage cannot follow the FP64 chain (FP32 rounding changes the
 samples), so at full size (32^4 MAG, the annealing workload) it is checked by
 properties and by one overrelaxation half-sweep recomputed by the oracle on
@@ -29,18 +32,18 @@ def test_anneal_matches_oracle(gauge, storage):
     ref = U.copy()
     V = int(np.prod(dims))
     G = O.identity_field(V) if gauge == "coulomb" else None
-    ctr = O.anneal(ref, dims, gauge, 1.5, 0.01, 12, nmicro=3, seed=4002, instance=0, sweep_counter=0, G=G)
+    ctr = O.anneal(ref, dims, gauge, 1.5, 1.5, 1, nmicro=3, seed=4002, instance=0, sweep_counter=0, G=G)
     if gauge == "coulomb":
         O.coulomb_fix_u0(ref, dims, G)
     fx = fixer([dims], gauge, storage)
     fx.upload(0, U)
-    fx.set_anneal(1.5, 0.01, 12, nmicro=3, seed=4002)
+    fx.set_anneal(1.5, 1.5, 1, nmicro=3, seed=4002)
     st, done = fx.sweep("anneal")
-    assert fx.get_sweep_index(0) == ctr == 12 * 4
+    assert fx.get_sweep_index(0) == ctr == 4
     out = fx.download(0)
     err = np.max(np.abs(out - ref))
-    say("max |gpu - oracle| after annealing", err)
-    assert err < 1e-10
+    say("max |gpu - oracle| after one annealing step", err)
+    assert err < 1e-8
     # then overrelaxation to theta < 1e-12 on both sides
     r = O.run(ref, dims, gauge, "or", omega=1.7, max_sweeps=3000, tol=1e-12, check_every=5, sweep_counter=ctr)
     fx.set_overrelax(1.7)
@@ -49,7 +52,44 @@ def test_anneal_matches_oracle(gauge, storage):
     fx.close()
     assert st == 0 and r.status == 0
     np.testing.assert_array_equal(done, r.sweeps_done.astype(np.int32))
-    assert np.max(np.abs(out - ref)) < 1e-9
+    assert np.max(np.abs(out - ref)) < 1e-7
+
+
+@pytest.mark.parametrize("storage", ["f64r18", "f64r12", "mixed"])
+@pytest.mark.parametrize("gauge", ["mag", "landau"])
+def test_long_anneal_keeps_invariants_and_converges(gauge, storage):
+    # 800 annealing sweeps with no periodic reprojection: the links must stay
+    # on SU(3) (12-real storage rebuilds the third row, which would let a norm
+    # defect grow exponentially under these large updates) and keep their
+    # gauge invariants; then overrelaxation converges
+    dims = (4, 4, 6, 4)
+    say("long anneal", gauge, storage)
+    U = I.smooth(dims, 0.7, 4004)
+    before = [O.wilson_loop(U, dims, r, t) for r, t in ((1, 1), (1, 2))]
+    fx = fixer([dims], gauge, storage, reunit_every=0)
+    fx.upload(0, U)
+    fx.set_anneal(1.5, 0.01, 200, nmicro=3, seed=4005)
+    fx.sweep("anneal")
+    assert fx.get_sweep_index(0) == 800
+    umean, umax = fx.unitarity()
+    say("unitarity after annealing: mean", umean, "max", umax)
+    f64 = storage != "mixed"
+    # FP64: rounding drift of at most 1e-15 per sweep (as for the oracle)
+    assert umax < (1e-15 * 800 if f64 else 2e-6)
+    fx.set_overrelax(1.7)
+    st, done = fx.sweep("or", max_sweeps=5000, tol=1e-12, check_every=5)
+    F, th = fx.measure(0)
+    out = fx.download(0)
+    fx.close()
+    assert st == 0
+    tol_inv = 1e-13 if f64 else 2e-6
+    np.testing.assert_allclose([O.wilson_loop(out, dims, r, t) for r, t in ((1, 1), (1, 2))], before, atol=tol_inv)
+    Fo, tho = O.measure(out, dims, gauge)
+    if f64:
+        assert abs(Fo - F) < 1e-12 and tho < 1e-12
+    else:
+        # the download rebuilds row 2 in FP64 from the FP32 rows, as the kernels do
+        assert abs(Fo - F) < 1e-9 and tho < 1e-11
 
 
 def test_anneal_resume_is_bit_identical():
@@ -119,13 +159,15 @@ def test_c4_mag_anneal_full_size():
     say("annealed: F", F_sa, "theta", th_sa, "OR half-sweep max err", err)
     assert err < 3e-5
     st, done = fx.sweep("or", max_sweeps=100000, tol=1e-12, check_every=10)
+    F0, th0 = fx.measure(0)
     fx.reunitarise()
     F, th = fx.measure(0)
     out = fx.download(0, reunitarise=True)
     fx.close()
-    say("after OR: status", st, "sweeps", done, "F", F, "theta", th)
-    assert st == 0
+    say("after OR: status", st, "sweeps", done, "F", F, "theta at stop", th0, "after reprojection", th)
+    assert st == 0 and th0 < 1e-12
     assert F > F_sa
     assert abs(O.plaquette(out, dims) - plaq) < 1e-6
     Fo, tho = O.measure(out, dims, "mag")
-    assert abs(Fo - F) < 1e-9 and tho < 1.5e-12
+    # the final FP32 rounding of the reprojected links moves theta by ~1e-12
+    assert abs(Fo - F) < 1e-9 and tho < 5e-12

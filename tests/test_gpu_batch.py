@@ -63,16 +63,18 @@ def test_c5_gribov_batch_full_size():
     fx.set_overrelax(1.7)
     fx.autotune(reps=1)
     st, done = fx.sweep("or", max_sweeps=50000, tol=1e-12, check_every=10)
-    fx.reunitarise()
     say("status", st, "sweeps per copy", done.tolist())
     assert st == 0
+    for k in range(len(shapes) * ncopy):
+        assert fx.measure(k)[1] < 1e-12  # every copy stopped below the tolerance
+    fx.reunitarise()
     Fs = np.zeros(len(shapes) * ncopy)
     k = 0
     for li, d in enumerate(shapes):
         for c in range(ncopy):
             F, th = fx.measure(k)
             Fs[k] = F
-            assert th < 1.5e-12
+            assert th < 5e-12  # after the final FP64 reprojection rounded to FP32
             if c in (0, ncopy - 1):
                 out = fx.download(k, reunitarise=True)
                 assert abs(O.plaquette(out, d) - plaq[li]) < 1e-6
@@ -88,8 +90,14 @@ def test_c5_gribov_batch_full_size():
     Fo = O.measure(U, d, "landau")[0]
     out = fx.download(0, reunitarise=True)
     fx.close()
-    same = np.max(np.abs((out[..., 0, 0, 0] + out[..., 1, 1, 0] + out[..., 2, 2, 0]) -
-                         (U[..., 0, 0, 0] + U[..., 1, 1, 0] + U[..., 2, 2, 0]))) < 1e-5
-    say("16^4 copy 0: F gpu", Fs[0], "oracle", Fo, "same Gribov copy", same)
+    # Re tr U(x) per link is invariant under the global transformations that
+    # the Landau condition leaves free; two runs in the same Gribov copy agree
+    # on it up to the residual of the stopping tolerance (about
+    # sqrt(theta) / lowest lattice Laplacian eigenvalue, ~1e-5 here) while
+    # distinct copies differ by far more
+    dtr = np.max(np.abs((out[..., 0, 0, 0] + out[..., 1, 1, 0] + out[..., 2, 2, 0]) -
+                        (U[..., 0, 0, 0] + U[..., 1, 1, 0] + U[..., 2, 2, 0])))
+    same = dtr < 1e-3
+    say("16^4 copy 0: F gpu", Fs[0], "oracle", Fo, "max |d Re tr U|", dtr, "same Gribov copy", same)
     if same:
         assert abs(Fs[0] - Fo) < 1e-9 * Fo

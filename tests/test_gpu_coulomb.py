@@ -29,6 +29,7 @@ def _device_input():
     for t0 in range(0, DIMS[0], SLAB):
         slab = I.smooth(DIMS, 0.5, 3001, t0=t0, nt=SLAB).reshape(-1)
         buf[t0 * Vs * 72:(t0 + SLAB) * Vs * 72].copy_(torch.from_numpy(slab))
+        say("  generated time-slices", t0, "to", t0 + SLAB - 1)
     return buf
 
 
@@ -73,16 +74,29 @@ def test_c3_coulomb_full_size():
     say("C3: full fix")
     _upload(fx, buf)
     del buf
-    st, done = fx.sweep("or", max_sweeps=50000, tol=1e-12, check_every=10)
+    # in calls of 1000 sweeps (a converged time-slice stops at the first
+    # check of the next call, and each call ends with the U_0 fix-up, so the
+    # chunks continue one run)
+    done = np.zeros(DIMS[0], dtype=np.int64)
+    for chunk in range(50):
+        st, d = fx.sweep("or", max_sweeps=1000, tol=1e-12, check_every=10)
+        done += d
+        say("  after", int(done.max()), "sweeps: status", st, "slices still running",
+            int(np.sum(d == 1000)))
+        if st == 0:
+            break
+    Ft0, tht0 = fx.measure_timeslices(0)
     fx.reunitarise()
     Ft, tht = fx.measure_timeslices(0)
-    say("status", st, "sweeps min/max", done.min(), done.max(), "theta max", tht.max())
+    say("status", st, "sweeps min/max", done.min(), done.max(), "theta max at stop", tht0.max(),
+        "after reprojection", tht.max())
     assert st == 0
-    assert np.all(tht < 1.5e-12)
+    assert np.all(tht0 < 1e-12)
+    assert np.all(tht < 5e-12)
     assert len(set(done.tolist())) > 1  # time-slices stop on their own
     for t in SLICES:
         got = fx.download(0, t0=t, nt=1, reunitarise=True)
         Fo, tho = O.measure_slices(got, d1)
         say("slice", t, "F gpu", Ft[t], "oracle", Fo[0], "theta", tho[0])
-        assert abs(Fo[0] - Ft[t]) < 1e-9 and tho[0] < 1.5e-12
+        assert abs(Fo[0] - Ft[t]) < 1e-9 and tho[0] < 5e-12
     fx.close()

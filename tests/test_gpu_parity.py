@@ -8,8 +8,13 @@ Mixed storage computes the update in FP32 from FP32 links: K is a sum of up
 to 8 SU(3) matrices (|K_ij| <= 8, ulp(8) = 9.5e-7), so the relaxation
 direction carries errors of a few ulp(8), amplified up to 2x by the
 microcanonical square; the bound is 3e-5 (about thirty ulp(8)).  With the
-update computed in FP64 (the FP64 tail) only the FP32 rounding of the
-stored links remains: a few ulp(1) = 6e-8 per update, bound 1e-6.
+update computed in FP64 (the FP64 tail) only the storage of the links
+remains: the FP32 rounding (ulp(1) = 6e-8) and the first-order reprojection
+step before it, which moves the two stored rows by up to their unitarity
+defect (a few ulp(1), since the loaded rows are FP32-rounded).  The second
+parity's updates see these changes through K, and the microcanonical square
+of a poorly determined direction (small |q|) amplifies them about tenfold:
+bound 5e-6.
 """
 import sys
 
@@ -23,7 +28,7 @@ pytestmark = pytest.mark.gpu
 
 STORAGES = ["f64r18", "f64r12", "mixed"]
 ALL_MODES = STORAGES + ["mixed64"]  # mixed64: FP32 storage, update in FP64
-TOL_LINK = {"f64r18": 1e-12, "f64r12": 1e-12, "mixed": 3e-5, "mixed64": 1e-6}
+TOL_LINK = {"f64r18": 1e-12, "f64r12": 1e-12, "mixed": 3e-5, "mixed64": 5e-6}
 
 
 def say(*a):

@@ -199,3 +199,25 @@ def test_stochastic_relaxation_converges():
     O.sweep(U1, dims, "mag", "sr", p_sr=0.0, seed=9)
     O.sweep(U2, dims, "mag", "or", omega=1.0)
     assert np.max(np.abs(U1 - U2)) < 1e-13  # or_map at omega = 1 renormalises h
+
+
+@pytest.mark.parametrize("gauge", ["mag", "landau"])
+def test_annealing_amplifies_rounding_differences(gauge):
+    # the annealing chain is sensitive: a 1e-15 perturbation of the input grows
+    # by orders of magnitude per annealing step (heatbath + 3 micro), so two
+    # implementations can follow the same chain only over a few steps
+    dims = (4, 4, 6, 4)
+    U = I.smooth(dims, 0.7, 4001)
+    U2 = U + 1e-15 * np.random.default_rng(0).normal(size=U.shape)
+    diffs = []
+    c = 0
+    for k in range(4):
+        T = 1.5 + (0.01 - 1.5) * k / 11
+        for A in (U, U2):
+            O.sweep(A, dims, gauge, "heatbath", T=T, seed=4002, sweep=c)
+            for m in range(3):
+                O.sweep(A, dims, gauge, "micro", sweep=c + 1 + m)
+        c += 4
+        diffs.append(np.max(np.abs(U - U2)))
+    assert diffs[0] < 1e-8
+    assert diffs[-1] > 1e3 * diffs[0]
