@@ -42,6 +42,12 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"mixed": 768, "f64r12": 1536, "f64r18": 2304}  # 8 links loaded + stored
 
 
+def fp64_policy():
+    upd = ("FP64 once theta < %g" % TAIL) if TAIL > 0 else "FP32 throughout"
+    return ("F/theta reductions, applying G to the links, reprojection every %d sweeps; update arithmetic %s"
+            % (REUNIT, upd))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -190,6 +196,8 @@ def main():
     ttt = {"mixed_s": [round(t, 4) for t in per_step[:len(SEEDS)]], "mixed_sweeps": sweeps[:len(SEEDS)]}
     if not args.no_fp64:
         f64 = make_fixer(gf, "f64r12")
+        f64.upload(0, inputs[0])
+        f64.autotune(reps=5)
         one_fix(f64, inputs[0])
         tt, sw = [], []
         for i in range(min(args.steps, len(SEEDS))):
@@ -220,8 +228,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "landau-32^4-eps0.5-seeds2001-2004-omega1.7-theta1e-12", "lattice": list(DIMS),
-                   "gauge": "landau", "storage": "fp32-12real", "fp64": "reductions, reprojection every %d, update "
-                   "once theta<%g" % (REUNIT, TAIL), "check_every": CHECK, "waves_per_site_group": lanes,
+                   "gauge": "landau", "storage": "fp32-12real", "fp64": fp64_policy(), "check_every": CHECK, "waves_per_site_group": lanes,
                    "status": status, "sweeps": sweeps},
         "hbm_gbs_effective": eff_gbs,
         "time_to_theta": ttt,

@@ -189,9 +189,11 @@ int gf_set_launch(gf_handle h, int waves_per_site, int block);
 
 /* Time the available variants of the OR half-sweep on the bound
    configuration, separately for each compute precision the configuration
-   uses (each variant runs `reps` real OR sweeps, which advance the fixing),
-   and keep the fastest.  *waves_per_site (of the precision doing most
-   sweeps) and *block (may be NULL) receive the choice. */
+   uses, and keep the one with the smallest median launch time.  `reps`
+   rounds visit every variant in turn, each visit running one untimed and
+   one timed OR sweep (real sweeps: they advance the fixing, 2 reps sweeps
+   per variant).  *waves_per_site (of the precision doing most sweeps) and
+   *block (may be NULL) receive the choice. */
 int gf_autotune(gf_handle h, int reps, int *waves_per_site, int *block);
 
 /* Kernel timing: while enabled, every half-sweep launch is bracketed by HIP

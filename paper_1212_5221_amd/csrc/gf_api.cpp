@@ -91,6 +91,7 @@ struct gf_ctx {
     double t_sum_ms[2] = {0.0, 0.0};
     int64_t t_count[2] = {0, 0};
     double t_min_ms[2] = {1e300, 1e300};
+    std::vector<float> *t_log = nullptr;  // autotuning: every launch duration
 
     bool use_graph = true;
     GraphCache graph;
@@ -207,9 +208,9 @@ void plan_layout(gf_ctx *h) {
                 u.h0 = 0;
                 u.n = (int32_t)I.Vh;
             }
-            const int per = (u.n + 255) / 256;
+            const int per = (u.n + gfs::MTILE_SITES - 1) / gfs::MTILE_SITES;
             u.mtile0 = mt;
-            mt += 2 * per;
+            mt += per;
             u.mtile1 = mt;
             tiles_min += (u.n + 63) / 64;
             h->units.push_back(u);
@@ -339,6 +340,7 @@ int drain_timing(gf_ctx *h) {
         h->t_sum_ms[p.ctd] += ms;
         h->t_count[p.ctd] += 1;
         h->t_min_ms[p.ctd] = std::min(h->t_min_ms[p.ctd], (double)ms);
+        if (h->t_log) h->t_log->push_back(ms);
         h->ev_pool.push_back(p.e0);
         h->ev_pool.push_back(p.e1);
     }
@@ -658,8 +660,7 @@ int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes) {
     std::vector<gfs::MTile> mt;
     for (int u = 0; u < h->nunits; ++u) {
         const gfs::UnitDev &U = h->units[u];
-        for (int p = 0; p < 2; ++p)
-            for (int32_t j = 0; j < U.n; j += 256) mt.push_back({u, p, j, 0});
+        for (int32_t j = 0; j < U.n; j += gfs::MTILE_SITES) mt.push_back({u, 0, j, 0});
     }
     HIPCHK(h, hipMemcpyAsync(h->ws + h->off_inst, idv.data(), sizeof(gfs::InstDev) * idv.size(), hipMemcpyHostToDevice,
                              h->stream));
@@ -1048,44 +1049,46 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
     const int64_t save_cnt[2] = {h->t_count[0], h->t_count[1]};
     HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_active), 1, h->nunits, h->stream));
     const int used = used_precisions(h);
+    // Rounds interleave the candidate shapes (drifts of clock or temperature
+    // hit all of them alike); each round runs one untimed sweep after the
+    // change of shape and one timed sweep (real OR sweeps: they advance the
+    // fixing).  The shape with the smallest median launch time wins.
     for (int ctd = 0; ctd < 2; ++ctd) {
         if (!(used & (1 << ctd))) continue;
-        int bestW = h->W[ctd];
-        double best = 1e300;
+        std::vector<int> Ws;
+        for (int W = 1; W <= 8; W *= 2)
+            if (gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, ctd, W)) Ws.push_back(W);
+        std::vector<std::vector<float>> times(Ws.size());
         h->force_ctd = ctd;
-        for (int W = 1; W <= 8; W *= 2) {
-            if (!gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, ctd, W)) continue;
-            rc = build_tiles(h, ctd, W);
-            // warm-up sweep, then timed sweeps (real OR sweeps: they advance the fixing)
-            if (rc == GF_OK) rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false, 0);
-            if (rc == GF_OK) rc = count_chunk(h, 1);
-            if (rc == GF_OK) rc = drain_timing(h);
-            if (rc) {
-                h->force_ctd = -1;
-                return rc;
-            }
-            h->timing = true;
-            h->t_sum_ms[0] = h->t_sum_ms[1] = 0.0;
-            h->t_count[0] = h->t_count[1] = 0;
-            h->t_min_ms[0] = h->t_min_ms[1] = 1e300;
-            for (int r = 0; r < reps && rc == GF_OK; ++r) {
+        for (int r = 0; r < reps && rc == GF_OK; ++r)
+            for (size_t k = 0; k < Ws.size() && rc == GF_OK; ++k) {
+                rc = build_tiles(h, ctd, Ws[k]);
+                if (rc == GF_OK) rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false, 0);
+                if (rc == GF_OK) rc = count_chunk(h, 1);
+                if (rc == GF_OK) rc = drain_timing(h);
+                if (rc) break;
+                h->timing = true;
+                h->t_log = &times[k];
                 rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false, 0);
                 if (rc == GF_OK) rc = count_chunk(h, 1);
+                if (rc == GF_OK) rc = drain_timing(h);
+                h->timing = was_timing;
+                h->t_log = nullptr;
             }
-            if (rc == GF_OK) rc = drain_timing(h);
-            h->timing = was_timing;
-            if (rc) {
-                h->force_ctd = -1;
-                return rc;
-            }
-            // the fastest launch: robust against interference from other work
-            const double ms = h->t_min_ms[ctd];
-            if (ms < best) {
-                best = ms;
-                bestW = W;
+        h->force_ctd = -1;
+        if (rc) return rc;
+        int bestW = h->W[ctd];
+        double best = 1e300;
+        for (size_t k = 0; k < Ws.size(); ++k) {
+            std::vector<float> &t = times[k];
+            if (t.empty()) continue;
+            std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+            const double med = t[t.size() / 2];
+            if (med < best) {
+                best = med;
+                bestW = Ws[k];
             }
         }
-        h->force_ctd = -1;
         rc = build_tiles(h, ctd, bestW);
         if (rc) return rc;
     }

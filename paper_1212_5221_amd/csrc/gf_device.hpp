@@ -186,6 +186,16 @@ __device__ __forceinline__ Q4<T> qmul(const Q4<T> &a, const Q4<T> &b) {
     return r;
 }
 
+// ---------------------------------------------------------------- launch
+// Workgroups are dispatched round-robin over the 8 XCDs; block b works on
+// tile xcd_tile(b, n), which gives every XCD a contiguous range of tiles so
+// that neighbouring tiles share an L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int q = n >> 3, r = n & 7;
+    const int x = b & 7, i = b >> 3;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // ---------------------------------------------------------------- storage
 // Link storage (per instance, parity-split structure of arrays):
 //   plane (p, mu) holds Vp = Vh rounded up to 16 sites of NCH 16-byte

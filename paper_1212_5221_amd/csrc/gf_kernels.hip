@@ -65,22 +65,30 @@ __device__ __forceinline__ cx<double> det3(const M3<double> &m) {
     return cadd(csub(a, b), c);
 }
 
-// Per site (both parities): F contribution of the forward links, theta of
-// the site; optional |1 - det U| of the four forward links.  Partials per tile.
+// Per site: F contribution of the forward links, theta of the site;
+// optional |1 - det U| of the four forward links.  A block covers the
+// MTILE_SITES half-sites of its tile in both parities (waves 0-1 parity 0,
+// waves 2-3 parity 1) and tiles are spread over the XCDs in contiguous
+// ranges: the backward links of the z, y and x directions are then mostly
+// forward links that this block or a recent one on the same XCD has just
+// brought into L2, and only the t-direction ones come from further away.
+// Partials per tile.
 template <int GAUGE, int ST>
 __global__ __launch_bounds__(MBLOCK) void k_measure(gfs::MeasureArgs a) {
     typedef Store<ST> SD;
     constexpr int NDIR = (GAUGE == gfs::COULOMB) ? 3 : 4;
     constexpr int MU0 = (GAUGE == gfs::COULOMB) ? 1 : 0;
+    static_assert(gfs::MTILE_SITES * 2 == MBLOCK, "a measure block covers its tile in both parities");
     __shared__ double sh[4];
-    const gfs::MTile tl = a.tiles[blockIdx.x];
+    const int tix = xcd_tile(blockIdx.x, gridDim.x);
+    const gfs::MTile tl = a.tiles[tix];
     const gfs::UnitDev U = a.unit[tl.unit];
     const gfs::InstDev I = a.inst[U.inst];
-    int32_t j = tl.j0 + threadIdx.x;
+    int32_t j = tl.j0 + (int32_t)(threadIdx.x % gfs::MTILE_SITES);
     const bool valid = j < U.n;
     if (!valid) j = U.n - 1;
     const int32_t h = U.h0 + j;
-    const int p = tl.parity;
+    const int p = (int)(threadIdx.x / gfs::MTILE_SITES);
     const Site s = site_of(I, h, p);
 
     double F = 0.0, th = 0.0, us = 0.0, um = 0.0;
@@ -155,7 +163,7 @@ __global__ __launch_bounds__(MBLOCK) void k_measure(gfs::MeasureArgs a) {
         bM = block_max(um, sh);
     }
     if (threadIdx.x == 0) {
-        double *o = a.partial + 4 * (int64_t)blockIdx.x;
+        double *o = a.partial + 4 * (int64_t)tix;
         o[0] = bF;
         o[1] = bT;
         o[2] = bU;

@@ -37,7 +37,11 @@ struct Tile {
     int32_t j0;
 };
 
-// a measure tile: sites [j0, j0 + 256) of parity p of one unit
+// half-sites per measure tile (a 256-thread block covers them in both parities)
+constexpr int MTILE_SITES = 128;
+
+// a measure tile: half-sites [j0, j0 + MTILE_SITES) of one unit, both
+// parities (parity is unused)
 struct MTile {
     int32_t unit;
     int32_t parity;

@@ -27,14 +27,6 @@ namespace gfd {
 
 constexpr int SWEEP_BLOCK = 256;
 
-__device__ __forceinline__ int xcd_tile(int b, int n) {
-    // workgroups are dispatched round-robin over 8 XCDs; give every XCD a
-    // contiguous range of tiles so neighbouring tiles share an L2
-    const int q = n >> 3, r = n & 7;
-    const int x = b & 7, i = b >> 3;
-    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
-
 // ---------------------------------------------------------------- updates
 template <typename T>
 __device__ __forceinline__ Q4<T> q_unit() {

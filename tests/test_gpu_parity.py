@@ -44,6 +44,16 @@ def fixer(dims_list, gauge, storage, **kw):
     return gf.GaugeFixer(dims_list, gauge=gauge, storage=storage, **kw)
 
 
+def f_orbit_tol(sweeps, V):
+    """Relative bound on F between a mixed-storage fix and the FP64 oracle's
+    fix of the same input (same Gribov copy).  Each update rounds the stored
+    rows of a link to FP32 (relative ~6e-8), which moves it off its gauge
+    orbit; F averages Re tr U over the 4V links, so these independent
+    roundings (two per link and sweep) add up like a random walk of
+    6e-8 sqrt(2 sweeps / (4V)); three standard deviations."""
+    return 3.0 * 6e-8 * np.sqrt(2.0 * sweeps / (4.0 * V))
+
+
 def f32_round(U):
     """the input as the mixed storage holds it (rows 0, 1 rounded to FP32, row 2 rebuilt in FP64)"""
     C = U[..., 0].astype(np.float32).astype(np.float64) + 1j * U[..., 1].astype(np.float32).astype(np.float64)
