@@ -119,6 +119,60 @@ def cpu_baseline(budget_s=12.0):
             "sample": "%d Landau OR sweeps (omega 1.7) of the 32^4 seed-2001 configuration, FP64, %.1f s" % (n, el)}
 
 
+def copy_ceiling(torch, nbytes, reps=20):
+    """A plain device-to-device copy that reads and writes nbytes (the bytes
+    one half-sweep reads and writes), median of reps timed copies: a measured
+    bandwidth ceiling beside the 8 TB/s peak."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    del x, y
+    return {"bytes": 2 * nbytes, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9, "kernel": "device copy (hipMemcpyAsync)"}
+
+
+def kernel_table(gf, I, nsweeps=20):
+    """Half-sweep launch time and effective bandwidth of every gauge x
+    storage x update on a 32^4 lattice (Coulomb: 32 time-slices of 32^3),
+    autotuned, nsweeps sweeps with kernel timing; one JSON line each."""
+    V = int(np.prod(DIMS))
+    U = I.smooth(DIMS, EPS, SEEDS[0])
+    link = {"mixed": 48, "f64r12": 96, "f64r18": 144}
+    for gauge in ("landau", "coulomb", "mag"):
+        nl = 6 if gauge == "coulomb" else 8
+        for storage in ("mixed", "f64r12", "f64r18"):
+            # algorithmic bytes per site update: links loaded and stored (+ G for Coulomb)
+            bps = 2 * nl * link[storage] + (2 * link[storage] if gauge == "coulomb" else 0)
+            for upd in ("or", "heatbath"):
+                fx = gf.GaugeFixer([DIMS], gauge=gauge, storage=storage, reunit_every=0, tail_theta=0.0)
+                fx.upload(0, U)
+                fx.set_overrelax(OMEGA)
+                fx.set_temperature(0.5)
+                fx.set_seed(7)
+                w, _ = fx.autotune(reps=5)
+                fx.upload(0, U)
+                fx.set_timing(True)
+                fx.sweep(upd, max_sweeps=nsweeps, tol=0.0, check_every=nsweeps)
+                n, ms = fx.kernel_time("all")
+                fx.set_timing(False)
+                fx.close()
+                gbs = bps * V / 2 / (ms * 1e-3) / 1e9
+                print(json.dumps({"gauge": gauge, "storage": storage, "update": upd, "waves_or": w,
+                                  "launches": n, "mean_launch_ms": round(ms, 5),
+                                  "bytes_per_site_update": bps, "GBs": round(gbs, 1),
+                                  "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}), flush=True)
+
+
 def golden_F():
     p = os.path.join(ROOT, "tests", "golden", "c2_landau_oracle.json")
     if not os.path.exists(p):
@@ -136,6 +190,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (scale for rocprof byte counters)")
+    ap.add_argument("--kernel-table", action="store_true",
+                    help="only time the half-sweep of every gauge, storage and update on 32^4 (one JSON line each)")
     ap.add_argument("--profile-sweeps", type=int, default=0,
                     help="only run this many OR sweeps of the workload (for profiler counter runs)")
     args = ap.parse_args()
@@ -155,6 +211,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}))
+        return
+    if args.kernel_table:
+        kernel_table(gf, I)
         return
     if args.profile_sweeps:
         # a fixed number of OR sweeps of seed 2001 in the benchmark's launch
@@ -245,6 +304,19 @@ def main():
         ttt["fp64_sweeps"] = sw
         ttt["speedup_mixed_vs_fp64"] = round(sum(tt) / sum(per_step[:len(tt)]), 3)
 
+    ceiling = copy_ceiling(torch, int(bytes_per_launch) // 2)
+    # the same input handed over from host memory (pageable numpy array):
+    # the PCIe-inclusive cost of a fix, reported beside the HBM-resident value
+    host_in = I.smooth(DIMS, EPS, SEEDS[0])
+    fx2 = make_fixer(gf, "mixed")
+    fx2.upload(0, host_in)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    fx2.upload(0, host_in)
+    torch.cuda.synchronize()
+    host_upload_ms = (time.perf_counter() - ts) * 1e3
+    fx2.close()
+    del host_in
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -265,12 +337,14 @@ def main():
                    "status": status, "sweeps": sweeps},
         "hbm_gbs_effective": eff_gbs,
         "time_to_theta": ttt,
+        "host_upload_ms": host_upload_ms,
         "F_vs_oracle": F_err,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(lanes),
                      "kernel": "k_sweep (half-sweep)", "bytes_per_launch": bytes_per_launch,
                      "mean_launch_ms": mean_ms, "launches": launches,
-                     "fp64_tail_launches": launches64, "fp64_tail_mean_ms": mean_ms64},
+                     "fp64_tail_launches": launches64, "fp64_tail_mean_ms": mean_ms64,
+                     "copy_ceiling": ceiling},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
