@@ -472,10 +472,12 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
         const int mu = MU0 + (fw ? l : l - NDIR);
         M3<AT> m, o;
         expand<ST, AT>(r[q], m);
-        if (fw)
+        if (fw) {
             apply_left(Ga, m, o, SD::ROWS);
-        else
+            if constexpr (SD::ROWS == 2) renormalise_rows(o);
+        } else {
             apply_right_dag(Ga, m, o, SD::ROWS);
+        }
         compress<ST, AT>(o, r[q]);
         if (valid) SD::store(plane_ptr<ST>(a.ws, I, fw ? p : 1 - p, mu), I.Vh, lh[q], r[q]);
     }
@@ -489,6 +491,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
         M3<AT> m, o;
         expand<ST, AT>(gr, m);
         apply_left(Ga, m, o, SD::ROWS);
+        if constexpr (SD::ROWS == 2) renormalise_rows(o);
         compress<ST, AT>(o, gr);
         if (valid) SD::store(gp, I.Vh, h, gr);
       }
