@@ -196,12 +196,15 @@ int gf_set_launch(gf_handle h, int waves_per_site, int block);
    *block (may be NULL) receive the choice. */
 int gf_autotune(gf_handle h, int reps, int *waves_per_site, int *block);
 
-/* Kernel timing: while enabled, every half-sweep launch is bracketed by HIP
-   events on the handle's stream (HIP graphs are not used meanwhile).
+/* Kernel timing: every: 0 off; n >= 1 brackets every n-th half-sweep launch
+   with HIP events recorded by the launch itself on the handle's stream
+   (n = 1: every launch; a larger odd n samples both parities at a fraction of
+   the event overhead).  HIP graphs are not used while timing is on.
+   GF_E_INVALID for every < 0.
    gf_kernel_time returns the number of timed half-sweep launches and their
-   mean duration in milliseconds since timing was last enabled; which: 0 all
+   mean duration in milliseconds since timing was last set; which: 0 all
    launches, 1 launches computing the update in FP32, 2 in FP64. */
-int gf_set_timing(gf_handle h, int enable);
+int gf_set_timing(gf_handle h, int every);
 int gf_kernel_time(gf_handle h, int which, int64_t *launches, double *mean_ms);
 
 /* HIP graph capture of the sweep loop between checks (1 = on, default). */

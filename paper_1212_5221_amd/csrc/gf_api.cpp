@@ -80,8 +80,10 @@ struct gf_ctx {
     int32_t *hstat = nullptr;
     double *hres = nullptr;
 
-    // timing
+    // timing: every time_every-th half-sweep launch is bracketed by events
     bool timing = false;
+    int time_every = 1;
+    uint64_t launch_seq = 0;
     std::vector<hipEvent_t> ev_pool;
     struct Pending {
         hipEvent_t e0, e1;
@@ -381,7 +383,8 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
         if (!fn) return fail(h, GF_E_INVALID, "no kernel variant for gauge %d update %d storage %d W %d", h->gauge, upd,
                              h->storage, h->W[ctd]);
         gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T, ctd, sweep_off);
-        const bool tm = h->timing && !capturing;
+        bool tm = false;
+        if (h->timing && !capturing) tm = (h->launch_seq++ % (uint64_t)h->time_every) == 0;
         if (tm) {
             // the launch itself records its start and stop events
             hipEvent_t e0 = take_event(h), e1 = take_event(h);
@@ -1043,6 +1046,21 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
     if (reps < 1) reps = 1;
     const int st = st_code(h->storage);
     const bool was_timing = h->timing;
+    const int was_every = h->time_every;
+    // every trial launch is timed; the caller's timing state comes back on
+    // every return path
+    struct Restore {
+        gf_ctx *h;
+        bool timing;
+        int every;
+        ~Restore() {
+            h->timing = timing;
+            h->time_every = every;
+            h->t_log = nullptr;
+            h->force_ctd = -1;
+        }
+    } restore{h, was_timing, was_every};
+    h->time_every = 1;
     rc = drain_timing(h);
     if (rc) return rc;
     const double save_sum[2] = {h->t_sum_ms[0], h->t_sum_ms[1]};
@@ -1101,11 +1119,14 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
     return GF_OK;
 }
 
-int gf_set_timing(gf_handle h, int enable) {
+int gf_set_timing(gf_handle h, int every) {
     if (!h) return GF_E_INVALID;
+    if (every < 0) return fail(h, GF_E_INVALID, "timing interval < 0");
     int rc = drain_timing(h);
     if (rc) return rc;
-    h->timing = enable != 0;
+    h->timing = every != 0;
+    h->time_every = every > 0 ? every : 1;
+    h->launch_seq = 0;
     h->t_sum_ms[0] = h->t_sum_ms[1] = 0.0;
     h->t_count[0] = h->t_count[1] = 0;
     h->t_min_ms[0] = h->t_min_ms[1] = 1e300;

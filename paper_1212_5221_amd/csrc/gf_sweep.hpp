@@ -231,6 +231,24 @@ __device__ __forceinline__ Q4<T> finish(const Q4<T> &h, const gfs::SweepArgs &a,
     return h;
 }
 
+// The W waves of a site group hold the same K (or MAG coefficients), so a
+// heatbath sample, which costs Philox draws, transcendental functions and a
+// rejection loop, is drawn by wave 0 alone and handed to the others through
+// LDS (one slot per subgroup, so one barrier per subgroup suffices).
+template <int W, int GROUPS, typename T>
+__device__ __forceinline__ void share_from_wave0(Q4<T> &g, int sg, int grp, int wv, int lane) {
+    if constexpr (W > 1) {
+        __shared__ T shg[3][GROUPS][4][64];
+        if (wv == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) shg[sg][grp][k][lane] = g.v[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) g.v[k] = shg[sg][grp][k][lane];
+    }
+}
+
 // ---------------------------------------------------------------- MAG blocks
 // block (i,j) of G U (forward link) and of U G^dag (backward link)
 template <typename T>
@@ -400,10 +418,12 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
             const Q4<CT> q = block_quat(K, i, jj);
             rng.sg = (uint64_t)sg;
             Q4<CT> g;
-            if constexpr (UPD == gfs::UPD_HEATBATH)
-                g = to_T<CT>(landau_heatbath(to_d(q), a.T, rng));
-            else
+            if constexpr (UPD == gfs::UPD_HEATBATH) {
+                if (wv == 0) g = to_T<CT>(landau_heatbath(to_d(q), a.T, rng));
+                share_from_wave0<W, GROUPS>(g, sg, grp, wv, lane);
+            } else {
                 g = finish<UPD, CT>(landau_relax(q), a, rng);
+            }
             left_sub(K, i, jj, g);
             left_sub(G, i, jj, g);
         }
@@ -440,10 +460,12 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
             }
             rng.sg = (uint64_t)sg;
             Q4<CT> g;
-            if constexpr (UPD == gfs::UPD_HEATBATH)
-                g = to_T<CT>(mag_heatbath(double(D), double(E), double(F), a.T, rng));
-            else
+            if constexpr (UPD == gfs::UPD_HEATBATH) {
+                if (wv == 0) g = to_T<CT>(mag_heatbath(double(D), double(E), double(F), a.T, rng));
+                share_from_wave0<W, GROUPS>(g, sg, grp, wv, lane);
+            } else {
                 g = finish<UPD, CT>(mag_relax(D, E, F), a, rng);
+            }
             left_sub(G, i, jj, g);
         }
     }

@@ -245,8 +245,9 @@ class GaugeFixer:
         self._check(self.lib.gf_autotune(self._h, int(reps), ctypes.byref(w), ctypes.byref(b)))
         return w.value, b.value
 
-    def set_timing(self, enable=True):
-        self._check(self.lib.gf_set_timing(self._h, 1 if enable else 0))
+    def set_timing(self, enable=True, every=1):
+        """time every `every`-th half-sweep launch with HIP events (enable=False: off)"""
+        self._check(self.lib.gf_set_timing(self._h, int(every) if enable else 0))
 
     def kernel_time(self, which="all"):
         """(launches, mean ms) of the timed half-sweeps: which = all | fp32 | fp64 update"""
