@@ -189,11 +189,12 @@ int gf_set_launch(gf_handle h, int waves_per_site, int block);
 
 /* Time the available variants of the OR half-sweep on the bound
    configuration, separately for each compute precision the configuration
-   uses, and keep the one with the smallest median launch time.  `reps`
-   rounds visit every variant in turn, each visit running one untimed and
-   one timed OR sweep (real sweeps: they advance the fixing, 2 reps sweeps
-   per variant).  *waves_per_site (of the precision doing most sweeps) and
-   *block (may be NULL) receive the choice. */
+   uses, and keep the one with the smallest median sweep time.  `reps`
+   rounds visit every variant in turn; a visit runs one untimed OR sweep and
+   then times 3 back-to-back OR sweeps with two events (real sweeps: they
+   advance the fixing, 4 reps sweeps per variant).  *waves_per_site (of the
+   precision doing most sweeps) and *block (may be NULL) receive the
+   choice. */
 int gf_autotune(gf_handle h, int reps, int *waves_per_site, int *block);
 
 /* Kernel timing: every: 0 off; n >= 1 brackets every n-th half-sweep launch

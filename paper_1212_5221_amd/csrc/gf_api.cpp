@@ -93,7 +93,6 @@ struct gf_ctx {
     double t_sum_ms[2] = {0.0, 0.0};
     int64_t t_count[2] = {0, 0};
     double t_min_ms[2] = {1e300, 1e300};
-    std::vector<float> *t_log = nullptr;  // autotuning: every launch duration
 
     bool use_graph = true;
     GraphCache graph;
@@ -342,7 +341,6 @@ int drain_timing(gf_ctx *h) {
         h->t_sum_ms[p.ctd] += ms;
         h->t_count[p.ctd] += 1;
         h->t_min_ms[p.ctd] = std::min(h->t_min_ms[p.ctd], (double)ms);
-        if (h->t_log) h->t_log->push_back(ms);
         h->ev_pool.push_back(p.e0);
         h->ev_pool.push_back(p.e1);
     }
@@ -1045,32 +1043,32 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
     if (rc) return rc;
     if (reps < 1) reps = 1;
     const int st = st_code(h->storage);
-    const bool was_timing = h->timing;
-    const int was_every = h->time_every;
-    // every trial launch is timed; the caller's timing state comes back on
-    // every return path
+    rc = drain_timing(h);
+    if (rc) return rc;
+    hipEvent_t e0 = take_event(h), e1 = take_event(h);
+    if (!e0 || !e1) return fail(h, GF_E_HIP, "hipEventCreate failed");
+    // trial sweeps are plain launches (no per-launch events); the caller's
+    // timing state and the events come back on every return path
     struct Restore {
         gf_ctx *h;
         bool timing;
-        int every;
+        hipEvent_t e0, e1;
         ~Restore() {
             h->timing = timing;
-            h->time_every = every;
-            h->t_log = nullptr;
             h->force_ctd = -1;
+            h->ev_pool.push_back(e0);
+            h->ev_pool.push_back(e1);
         }
-    } restore{h, was_timing, was_every};
-    h->time_every = 1;
-    rc = drain_timing(h);
-    if (rc) return rc;
-    const double save_sum[2] = {h->t_sum_ms[0], h->t_sum_ms[1]};
-    const int64_t save_cnt[2] = {h->t_count[0], h->t_count[1]};
+    } restore{h, h->timing, e0, e1};
+    h->timing = false;
     HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_active), 1, h->nunits, h->stream));
     const int used = used_precisions(h);
     // Rounds interleave the candidate shapes (drifts of clock or temperature
-    // hit all of them alike); each round runs one untimed sweep after the
-    // change of shape and one timed sweep (real OR sweeps: they advance the
-    // fixing).  The shape with the smallest median launch time wins.
+    // hit all of them alike).  A visit switches the shape, runs one untimed
+    // OR sweep, then times kSweeps back-to-back OR sweeps between two events
+    // (real sweeps: they advance the fixing), so the figure is the sweep
+    // throughput including launch gaps.  The smallest median wins.
+    constexpr int kSweeps = 3;
     for (int ctd = 0; ctd < 2; ++ctd) {
         if (!(used & (1 << ctd))) continue;
         std::vector<int> Ws;
@@ -1078,23 +1076,25 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
             if (gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, ctd, W)) Ws.push_back(W);
         std::vector<std::vector<float>> times(Ws.size());
         h->force_ctd = ctd;
-        for (int r = 0; r < reps && rc == GF_OK; ++r)
-            for (size_t k = 0; k < Ws.size() && rc == GF_OK; ++k) {
+        for (int r = 0; r < reps; ++r)
+            for (size_t k = 0; k < Ws.size(); ++k) {
                 rc = build_tiles(h, ctd, Ws[k]);
                 if (rc == GF_OK) rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false, 0);
                 if (rc == GF_OK) rc = count_chunk(h, 1);
-                if (rc == GF_OK) rc = drain_timing(h);
-                if (rc) break;
-                h->timing = true;
-                h->t_log = &times[k];
-                rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false, 0);
-                if (rc == GF_OK) rc = count_chunk(h, 1);
-                if (rc == GF_OK) rc = drain_timing(h);
-                h->timing = was_timing;
-                h->t_log = nullptr;
+                if (rc) return rc;
+                HIPCHK(h, hipEventRecord(e0, h->cur));
+                for (int i = 0; i < kSweeps && rc == GF_OK; ++i) {
+                    rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false, 0);
+                    if (rc == GF_OK) rc = count_chunk(h, 1);
+                }
+                if (rc) return rc;
+                HIPCHK(h, hipEventRecord(e1, h->cur));
+                HIPCHK(h, hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+                times[k].push_back(ms / kSweeps);
             }
         h->force_ctd = -1;
-        if (rc) return rc;
         int bestW = h->W[ctd];
         double best = 1e300;
         for (size_t k = 0; k < Ws.size(); ++k) {
@@ -1109,10 +1109,6 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
         }
         rc = build_tiles(h, ctd, bestW);
         if (rc) return rc;
-    }
-    for (int v = 0; v < 2; ++v) {
-        h->t_sum_ms[v] = save_sum[v];
-        h->t_count[v] = save_cnt[v];
     }
     if (lanes_per_site) *lanes_per_site = h->W[dominant_ctd(h)];
     if (block) *block = gfl::SWEEP_THREADS;
