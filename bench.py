@@ -53,8 +53,8 @@ BYTES_PER_SITE = {"mixed": 768, "f64r12": 1536, "f64r18": 2304}  # 8 links loade
 COUNTER_SOURCES = ("paper_1212_5221_amd/csrc/gf_sweep.hpp", "paper_1212_5221_amd/csrc/gf_device.hpp",
                    "paper_1212_5221_amd/csrc/gf_shared.hpp", "paper_1212_5221_amd/csrc/gf_sweep_landau.hip",
                    "paper_1212_5221_amd/build.py")
-COUNTER_DIGEST = "b6e25d5ba1b034af"
-COUNTER_TRAFFIC = {1: 402959070, 2: 402955384, 4: 402959479}
+COUNTER_DIGEST = "b42b1e37604a006f"
+COUNTER_TRAFFIC = {1: 402906886, 2: 402935967, 4: 402952145}
 
 
 def kernel_digest():
@@ -244,6 +244,7 @@ def main():
     torch.cuda.synchronize()
 
     fx = make_fixer(gf, "mixed")
+    fx.upload(0, inputs[0])  # autotune on the workload's data (it runs real sweeps)
     lanes, _ = fx.autotune(reps=10)
     log("autotune: waves per site group", lanes)
     for w in range(args.warmup):

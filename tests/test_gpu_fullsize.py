@@ -28,12 +28,15 @@ DIMS = (32, 32, 32, 32)
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_landau_oracle.json")
 
 
-def bench_fixer(storage="mixed"):
+def bench_fixer(U, storage="mixed"):
+    """the benchmark's fixer, autotuned on U as bench.py does; U uploaded"""
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
     from paper_1212_5221_amd import gf
     fx = bench.make_fixer(gf, storage)
-    fx.autotune(reps=1)
+    fx.upload(0, U)
+    fx.autotune(reps=10)
+    fx.upload(0, U)
     return fx
 
 
@@ -53,8 +56,7 @@ def _site_links(U, dims, s):
 def test_c2_one_halfsweep_sampled_sites():
     say("C2 full-size half-sweep, sampled sites")
     U = I.smooth(DIMS, 0.5, 2001)
-    fx = bench_fixer()
-    fx.upload(0, U)
+    fx = bench_fixer(U)
     fx.halfsweep("or", 0)
     out = fx.download(0)
     fx.close()
@@ -81,8 +83,7 @@ def test_c2_full_fix_properties():
     say("C2 full fix, seed 2001")
     U = I.smooth(DIMS, 0.5, 2001)
     before = [O.wilson_loop(U, DIMS, r, t) for r, t in ((1, 1), (1, 2))]
-    fx = bench_fixer()
-    fx.upload(0, U)
+    fx = bench_fixer(U)
     st, done = fx.sweep("or", max_sweeps=50000, tol=1e-12, check_every=10)
     th0 = fx.measure(0)[1]
     fx.reunitarise()
