@@ -92,6 +92,40 @@ def test_long_anneal_keeps_invariants_and_converges(gauge, storage):
         assert abs(Fo - F) < 1e-9 and tho < 1e-11
 
 
+@pytest.mark.parametrize("gauge", ["mag", "landau"])
+def test_cooling_pipeline_matches_oracle(gauge):
+    # annealing (one step, see above), then stochastic relaxation (p = 0.5,
+    # same Philox streams; unlike annealing its dynamics contract, so the two
+    # chains stay within rounding), then overrelaxation to theta < 1e-12
+    dims = (4, 4, 6, 4)
+    say("cooling pipeline", gauge)
+    U = I.smooth(dims, 0.7, 4001)
+    ref = U.copy()
+    ctr = O.anneal(ref, dims, gauge, 1.5, 1.5, 1, nmicro=3, seed=4002)
+    r1 = O.run(ref, dims, gauge, "sr", max_sweeps=300, tol=0.0, check_every=300, p_sr=0.5, seed=4003,
+               sweep_counter=ctr)
+    r2 = O.run(ref, dims, gauge, "or", omega=1.7, max_sweeps=3000, tol=1e-12, check_every=5,
+               sweep_counter=r1.sweep_counter)
+    fx = fixer([dims], gauge, "f64r18")
+    fx.upload(0, U)
+    fx.set_anneal(1.5, 1.5, 1, nmicro=3, seed=4002)
+    fx.sweep("anneal")
+    fx.set_seed(4003)
+    fx.set_stochastic(0.5)
+    fx.sweep("sr", max_sweeps=300, tol=0.0, check_every=300)
+    assert fx.get_sweep_index(0) == r1.sweep_counter
+    mid = fx.download(0)
+    fx.set_overrelax(1.7)
+    st, done = fx.sweep("or", max_sweeps=3000, tol=1e-12, check_every=5)
+    out = fx.download(0)
+    fx.close()
+    say("SR stage: theta", O.measure(mid, dims, gauge)[1], "OR sweeps gpu", done.tolist(),
+        "oracle", r2.sweeps_done.tolist(), "max |gpu - oracle|", np.max(np.abs(out - ref)))
+    assert st == 0 and r2.status == 0
+    np.testing.assert_array_equal(done, r2.sweeps_done.astype(np.int32))
+    assert np.max(np.abs(out - ref)) < 1e-8
+
+
 def test_anneal_resume_is_bit_identical():
     # checkpoint/resume: the random streams depend only on (seed, instance,
     # sweep index, site), so two halves with the sweep index carried over

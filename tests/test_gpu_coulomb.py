@@ -90,7 +90,8 @@ def test_c3_full_fix(c3):
     # modes of a 64^3 slice decay by about 1 - c omega lambda_min per sweep,
     # and lambda_min varies between slices): most stop between 30k and 100k
     # sweeps, a few need longer.  The test runs 100k sweeps and checks every
-    # stopped slice, and that the slices still running keep converging.
+    # stopped slice, and that the slices still running are close and keep
+    # stopping.
     fx, buf = c3
     say("C3: full fix")
     _upload(fx, buf)
@@ -117,8 +118,11 @@ def test_c3_full_fix(c3):
     assert np.all(tht0[stopped] < 1e-12)
     assert len(set(done[stopped].tolist())) > 1  # time-slices stop on their own
     if st != 0:
-        # the slices still running are converging: theta fell over the last 20k sweeps
-        assert np.all(hist[-1][~stopped] < 0.5 * hist[-11][~stopped])
+        # the slices still running are close (theta is not monotonic under
+        # overrelaxation, so no per-slice trend is asserted) and slices keep
+        # stopping: fewer run now than 20k sweeps ago
+        assert np.all(hist[-1][~stopped] < 1e-6)
+        assert np.sum(~stopped) < np.sum(hist[-11] >= 1e-12)
     fx.reunitarise()
     Ft, tht = fx.measure_timeslices(0)
     assert np.all(tht[stopped] < 5e-12)
