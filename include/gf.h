@@ -79,7 +79,8 @@ void gf_destroy(gf_handle h);
 const char *gf_last_error(gf_handle h);
 
 /* Add a lattice instance of extents dims = {Nt, Nx, Ny, Nz}.  Every extent
-   must be even and >= 2 (checkerboard with periodic boundaries); otherwise
+   must be even and >= 2 (checkerboard with periodic boundaries) and the
+   instance below 2^29 sites (half-site indices fit 28 bits); otherwise
    GF_E_DIMS.  *inst receives the instance number (0, 1, ...).  Only before
    gf_bind_workspace.  Instances are independent problems (Gribov copies,
    uneven lattices) swept together with per-instance stopping. */
