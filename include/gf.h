@@ -209,6 +209,22 @@ int gf_autotune(gf_handle h, int reps, int *waves_per_site, int *block);
 int gf_set_timing(gf_handle h, int every);
 int gf_kernel_time(gf_handle h, int which, int64_t *launches, double *mean_ms);
 
+/* Infinity-Cache grouping (an MI355X device has a 256 MB last-level cache
+   in front of HBM).  Inside gf_sweep, consecutive units (instances, or
+   Coulomb time-slices) whose working sets add up to at most `bytes` form a
+   group, and each group runs the whole chunk of check_every sweeps before
+   the next group starts, so a group's links stay in the cache across its
+   sweeps.  Units are independent, so every unit goes through the same
+   sweeps and checks as without grouping and the results are identical; a
+   unit larger than the budget is a group of its own.  Working set of a unit:
+   8 link planes over its half-sites (Coulomb: 6 spatial planes and the 2
+   accumulator planes), 48 / 96 / 144 bytes per link.  bytes = 0 turns
+   grouping off; default 224 MiB.  GF_E_INVALID for bytes < 0.  Annealing
+   (GF_ANNEAL) is never grouped.  gf_cache_groups returns the number of
+   groups of the bound configuration. */
+int gf_set_cache_budget(gf_handle h, int64_t bytes);
+int gf_cache_groups(gf_handle h, int32_t *groups);
+
 /* HIP graph capture of the sweep loop between checks (1 = on, default). */
 int gf_set_graph(gf_handle h, int enable);
 

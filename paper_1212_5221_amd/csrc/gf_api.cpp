@@ -96,6 +96,13 @@ struct gf_ctx {
 
     bool use_graph = true;
     GraphCache graph;
+    // Infinity-Cache groups: consecutive units whose working sets together
+    // fit cache_budget bytes; inside gf_sweep each group runs the whole chunk
+    // of sweeps before the next group starts (units are independent, so
+    // every unit's sequence of sweeps is unchanged)
+    int64_t cache_budget = (int64_t)224 << 20;
+    std::vector<int> grp_u0;         // group g = units [grp_u0[g], grp_u0[g + 1])
+    std::vector<int32_t> tile_u0[2]; // per compute precision: first tile of each unit (+ end)
 
     // from the last check: active units, of which in the FP64 tail
     int n_active = 0, n_tail = 0;
@@ -267,8 +274,12 @@ gfs::InstDev inst_dev(const InstHost &I) {
 int build_tiles(gf_ctx *h, int ctd, int W) {
     const int spb = gfl::SWEEP_THREADS / W;
     std::vector<gfs::Tile> t;
-    for (int u = 0; u < h->nunits; ++u)
+    h->tile_u0[ctd].assign(h->nunits + 1, 0);
+    for (int u = 0; u < h->nunits; ++u) {
+        h->tile_u0[ctd][u] = (int32_t)t.size();
         for (int32_t j = 0; j < h->units[u].n; j += spb) t.push_back({u, j});
+    }
+    h->tile_u0[ctd][h->nunits] = (int32_t)t.size();
     if ((int64_t)t.size() > h->max_tiles) return fail(h, GF_E_INVALID, "tile table overflow");
     HIPCHK(h, hipMemcpyAsync(h->ws + h->off_tiles[ctd], t.data(), sizeof(gfs::Tile) * t.size(), hipMemcpyHostToDevice,
                              h->stream));
@@ -301,12 +312,45 @@ int check_unbound(gf_ctx *h) {
     return GF_OK;
 }
 
-gfs::SweepArgs sweep_args(gf_ctx *h, int parity, int fp64_select, double T, int ctd, int sweep_off) {
+// bytes a unit's sweeps touch: 8 link planes over its half-sites (Coulomb:
+// 6 spatial planes and the 2 accumulator planes)
+int64_t unit_bytes(const gf_ctx *h, int u) {
+    const int st = st_code(h->storage);
+    const int64_t link = (st == gfs::ST_F32R12) ? 48 : (st == gfs::ST_F64R12 ? 96 : 144);
+    return 8 * (int64_t)h->units[u].n * link;
+}
+
+void build_groups(gf_ctx *h) {
+    h->grp_u0.assign(1, 0);
+    int64_t acc = 0;
+    for (int u = 0; u < h->nunits; ++u) {
+        const int64_t b = unit_bytes(h, u);
+        if (h->cache_budget > 0 && u > h->grp_u0.back() && acc + b > h->cache_budget) {
+            h->grp_u0.push_back(u);
+            acc = 0;
+        }
+        acc += b;
+    }
+    if (h->cache_budget <= 0) h->grp_u0.assign(1, 0);
+    h->grp_u0.push_back(h->nunits);
+}
+
+int ngroups(const gf_ctx *h) { return (int)h->grp_u0.size() - 1; }
+
+// grp < 0: every tile; else the tiles of group grp
+gfs::SweepArgs sweep_args(gf_ctx *h, int parity, int fp64_select, double T, int ctd, int sweep_off, int grp,
+                          int *ntiles) {
     gfs::SweepArgs a;
     a.ws = h->ws;
     a.inst = wsp<gfs::InstDev>(h, h->off_inst);
     a.unit = wsp<gfs::UnitDev>(h, h->off_unit);
     a.tiles = wsp<gfs::Tile>(h, h->off_tiles[ctd]);
+    *ntiles = h->ntiles[ctd];
+    if (grp >= 0) {
+        const int32_t t0 = h->tile_u0[ctd][h->grp_u0[grp]], t1 = h->tile_u0[ctd][h->grp_u0[grp + 1]];
+        a.tiles += t0;
+        *ntiles = t1 - t0;
+    }
     a.active = wsp<int32_t>(h, h->off_active);
     a.fp64 = wsp<int32_t>(h, h->off_fp64);
     a.sweep_ix = wsp<uint64_t>(h, h->off_sweepix);
@@ -349,7 +393,7 @@ int drain_timing(gf_ctx *h) {
 }
 
 // one half-sweep of update `upd` (gfs code) at temperature T on all active units
-int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sweep_off) {
+int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sweep_off, int grp = -1) {
     const int st = st_code(h->storage);
     const bool mixed = (h->storage == GF_MIXED_F32_R12);
     const bool hb = (upd == gfs::UPD_HEATBATH || upd == gfs::UPD_SR);
@@ -380,7 +424,9 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
         gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, st, ctd, h->W[ctd]);
         if (!fn) return fail(h, GF_E_INVALID, "no kernel variant for gauge %d update %d storage %d W %d", h->gauge, upd,
                              h->storage, h->W[ctd]);
-        gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T, ctd, sweep_off);
+        int nt = 0;
+        gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T, ctd, sweep_off, grp, &nt);
+        if (nt <= 0) continue;
         bool tm = false;
         if (h->timing && !capturing) tm = (h->launch_seq++ % (uint64_t)h->time_every) == 0;
         if (tm) {
@@ -388,7 +434,7 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
             hipEvent_t e0 = take_event(h), e1 = take_event(h);
             if (!e0 || !e1) return fail(h, GF_E_HIP, "hipEventCreate failed");
             void *args[] = {&a};
-            HIPCHK(h, hipExtLaunchKernel(reinterpret_cast<const void *>(fn), dim3((unsigned)h->ntiles[ctd]),
+            HIPCHK(h, hipExtLaunchKernel(reinterpret_cast<const void *>(fn), dim3((unsigned)nt),
                                          dim3(gfl::SWEEP_THREADS), args, 0, h->cur, e0, e1, 0));
             h->ev_pending.push_back({e0, e1, launches[k].ctd});
             if (h->ev_pending.size() > 4096) {
@@ -396,38 +442,58 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
                 if (rc) return rc;
             }
         } else {
-            fn<<<dim3((unsigned)h->ntiles[ctd]), dim3(gfl::SWEEP_THREADS), 0, h->cur>>>(a);
+            fn<<<dim3((unsigned)nt), dim3(gfl::SWEEP_THREADS), 0, h->cur>>>(a);
             HIPCHK(h, hipGetLastError());
         }
     }
     return GF_OK;
 }
 
-// reprojection of every link (and Coulomb accumulator); inside gf_sweep
-// (only_active) stopped units are skipped, so they keep the links their
-// stopping check measured
-int launch_reunit_all(gf_ctx *h, bool only_active) {
+// reprojection of the links (and Coulomb accumulator) of units [u0, u1);
+// inside gf_sweep (only_active) stopped units are skipped, so they keep the
+// links their stopping check measured
+int launch_reunit_units(gf_ctx *h, bool only_active, int u0, int u1) {
     const int st = st_code(h->storage);
     const int32_t *act = only_active ? wsp<int32_t>(h, h->off_active) : nullptr;
     for (auto &I : h->inst) {
-        HIPCHK(h, gfl::reunit(st, h->ws, I.links_off, 8, (int32_t)I.Vh, (int32_t)I.Vp, act, I.unit0, I.nunits,
-                              h->cur));
+        const int a = std::max(u0, (int)I.unit0), b = std::min(u1, (int)(I.unit0 + I.nunits));
+        if (a >= b) continue;
+        const int32_t h_lo = h->units[a].h0, h_hi = h->units[b - 1].h0 + h->units[b - 1].n;
+        HIPCHK(h, gfl::reunit(st, h->ws, I.links_off, 8, (int32_t)I.Vh, (int32_t)I.Vp, h_lo, h_hi - h_lo, act,
+                              I.unit0, I.nunits, h->cur));
         if (I.g_off >= 0)
-            HIPCHK(h, gfl::reunit(st, h->ws, I.g_off, 2, (int32_t)I.Vh, (int32_t)I.Vp, act, I.unit0, I.nunits,
-                                  h->cur));
+            HIPCHK(h, gfl::reunit(st, h->ws, I.g_off, 2, (int32_t)I.Vh, (int32_t)I.Vp, h_lo, h_hi - h_lo, act,
+                                  I.unit0, I.nunits, h->cur));
     }
     return GF_OK;
 }
 
+int launch_reunit_all(gf_ctx *h, bool only_active) { return launch_reunit_units(h, only_active, 0, h->nunits); }
+
 // one full sweep (both parities) + bookkeeping [+ reprojection]
 // one full sweep (both parities) [+ reprojection]; sweep_off is the sweep's
 // position in its chunk (random counter offset), counted by count_chunk
-int launch_sweep(gf_ctx *h, int upd, double T, bool reunit_now, bool capturing, int sweep_off) {
+int launch_sweep(gf_ctx *h, int upd, double T, bool reunit_now, bool capturing, int sweep_off, int grp = -1) {
     for (int p = 0; p < 2; ++p) {
-        int rc = launch_half(h, upd, p, T, capturing, sweep_off);
+        int rc = launch_half(h, upd, p, T, capturing, sweep_off, grp);
         if (rc) return rc;
     }
-    if (reunit_now) return launch_reunit_all(h, true);
+    if (!reunit_now) return GF_OK;
+    if (grp < 0) return launch_reunit_all(h, true);
+    return launch_reunit_units(h, true, h->grp_u0[grp], h->grp_u0[grp + 1]);
+}
+
+// n sweeps of every unit, chunk positions k0 .. k0 + n - 1; with several
+// cache groups, group by group
+int enqueue_chunk(gf_ctx *h, int upd, int n, int k0, bool capturing) {
+    const int R = h->reunit_every;
+    const int ng = ngroups(h);
+    for (int g = 0; g < ng; ++g)
+        for (int i = 0; i < n; ++i) {
+            const bool rn = (R > 0) && ((k0 + i + 1) % R == 0);
+            int rc = launch_sweep(h, upd, h->T, rn, capturing, i, ng > 1 ? g : -1);
+            if (rc) return rc;
+        }
     return GF_OK;
 }
 
@@ -482,11 +548,8 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
     // when R divides the chunk boundary pattern identically
     const bool graph_ok = h->use_graph && !h->timing && chunk_is_full && (R == 0 || (n % R == 0 && k0 % R == 0));
     if (!graph_ok) {
-        for (int i = 0; i < n; ++i) {
-            const bool rn = (R > 0) && ((k0 + i + 1) % R == 0);
-            int rc = launch_sweep(h, upd, h->T, rn, false, i);
-            if (rc) return rc;
-        }
+        int rc = enqueue_chunk(h, upd, n, k0, false);
+        if (rc) return rc;
         return count_chunk(h, n);
     }
     int tailkey = 0;
@@ -499,11 +562,7 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
         if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
         HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
         h->cur = h->cap;
-        int rc = GF_OK;
-        for (int i = 0; i < n && rc == GF_OK; ++i) {
-            const bool rn = (R > 0) && ((i + 1) % R == 0);
-            rc = launch_sweep(h, upd, h->T, rn, true, i);
-        }
+        int rc = enqueue_chunk(h, upd, n, 0, true);
         if (rc == GF_OK) rc = count_chunk(h, n);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(h->cap, &gr);
@@ -686,6 +745,7 @@ int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes) {
     h->n_active = h->nunits;
     h->n_tail = (h->tail_theta >= 1e300) ? h->nunits : 0;
     h->bound = true;
+    build_groups(h);
     rc = build_tiles(h, 0, default_W_for(h, 0));
     if (rc == GF_OK) rc = build_tiles(h, 1, default_W_for(h, 1));
     if (rc) {
@@ -1146,6 +1206,25 @@ int gf_kernel_time(gf_handle h, int which, int64_t *launches, double *mean_ms) {
     }
     if (launches) *launches = n;
     if (mean_ms) *mean_ms = n ? ms / (double)n : 0.0;
+    return GF_OK;
+}
+
+int gf_set_cache_budget(gf_handle h, int64_t bytes) {
+    if (!h) return GF_E_INVALID;
+    if (bytes < 0) return fail(h, GF_E_INVALID, "cache budget < 0");
+    h->cache_budget = bytes;
+    if (h->bound) {
+        build_groups(h);
+        h->graph.clear();
+    }
+    return GF_OK;
+}
+
+int gf_cache_groups(gf_handle h, int32_t *groups) {
+    if (!h) return GF_E_INVALID;
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (groups) *groups = ngroups(h);
     return GF_OK;
 }
 

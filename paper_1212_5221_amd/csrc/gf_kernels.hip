@@ -265,22 +265,22 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int n) {
 // reproject `count` vectors-of-links: every (plane, site) of the given
 // storage region [base, base + nplanes planes of Vh sites)
 template <int ST>
-__global__ __launch_bounds__(MBLOCK) void k_reunit(char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp,
-                                                   const int32_t *active, int32_t unit0, int32_t hper) {
+__global__ __launch_bounds__(MBLOCK) void k_reunit(char *ws, int64_t off, int32_t nplanes, int32_t Vp, int32_t h_lo,
+                                                   int32_t nh, const int32_t *active, int32_t unit0, int32_t hper) {
     typedef Store<ST> SD;
     const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
-    if (idx >= (int64_t)nplanes * Vh) return;
-    const int32_t pl = (int32_t)(idx / Vh), h = (int32_t)(idx - (int64_t)pl * Vh);
+    if (idx >= (int64_t)nplanes * nh) return;
+    const int32_t pl = (int32_t)(idx / nh), h = h_lo + (int32_t)(idx - (int64_t)pl * nh);
     // a stopped unit keeps the links it stopped with
     if (active && !active[unit0 + h / hper]) return;
     typename SD::V *base = reinterpret_cast<typename SD::V *>(ws + off) + (int64_t)pl * SD::NCH * Vp;
     typename SD::S r[SD::NR];
-    SD::load(base, Vh, h, r);
+    SD::load(base, 0, h, r);
     M3<double> m;
     expand<ST, double>(r, m);
     reproject(m);
     compress<ST, double>(m, r);
-    SD::store(base, Vh, h, r);
+    SD::store(base, 0, h, r);
 }
 
 // identity into the Coulomb accumulator (2 parity planes)
@@ -439,16 +439,17 @@ hipError_t fill_i32(int32_t *p, int32_t v, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp, const int32_t *active,
-                  int32_t unit0, int32_t nunits, hipStream_t s) {
-    const int64_t n = (int64_t)nplanes * Vh;
+hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp, int32_t h_lo, int32_t nh,
+                  const int32_t *active, int32_t unit0, int32_t nunits, hipStream_t s) {
+    const int64_t n = (int64_t)nplanes * nh;
+    if (n <= 0) return hipSuccess;
     const int32_t hper = Vh / nunits;
     if (st == gfs::ST_F64R18)
-        k_reunit<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh, Vp, active, unit0, hper);
+        k_reunit<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vp, h_lo, nh, active, unit0, hper);
     else if (st == gfs::ST_F64R12)
-        k_reunit<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh, Vp, active, unit0, hper);
+        k_reunit<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vp, h_lo, nh, active, unit0, hper);
     else
-        k_reunit<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vh, Vp, active, unit0, hper);
+        k_reunit<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vp, h_lo, nh, active, unit0, hper);
     return hipGetLastError();
 }
 

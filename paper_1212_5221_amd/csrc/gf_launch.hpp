@@ -26,10 +26,11 @@ hipError_t finalize_decide(int nunits, const gfs::UnitDev *units, const double *
 hipError_t count_sweep(int ninst, const gfs::InstDev *inst, const int32_t *active, int32_t *sweeps_done,
                        uint64_t *sweep_ix, int32_t n, hipStream_t s);
 hipError_t fill_i32(int32_t *p, int32_t v, int n, hipStream_t s);
-// reprojection of nplanes link planes; with `active`, half-sites of stopped
-// units (unit0 + h / (Vh / nunits)) are left as they are
-hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp, const int32_t *active,
-                  int32_t unit0, int32_t nunits, hipStream_t s);
+// reprojection of half-sites [h_lo, h_lo + nh) of nplanes link planes; with
+// `active`, half-sites of stopped units (unit0 + h / (Vh / nunits)) are left
+// as they are
+hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, int32_t Vp, int32_t h_lo, int32_t nh,
+                  const int32_t *active, int32_t unit0, int32_t nunits, hipStream_t s);
 hipError_t set_identity(int st, char *ws, int64_t off, int32_t Vh, int32_t Vp, hipStream_t s);
 hipError_t convert_in(int st, char *ws, const gfs::InstDev &I, const double *src, int64_t s0, int64_t ns,
                       hipStream_t s);

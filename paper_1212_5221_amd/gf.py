@@ -87,6 +87,8 @@ def load():
     L.gf_set_timing.argtypes = [vp, ci]
     L.gf_kernel_time.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_int64), dp]
     L.gf_set_graph.argtypes = [vp, ci]
+    L.gf_set_cache_budget.argtypes = [vp, ctypes.c_int64]
+    L.gf_cache_groups.argtypes = [vp, i32p]
     _lib = L
     return L
 
@@ -256,6 +258,15 @@ class GaugeFixer:
         ms = ctypes.c_double()
         self._check(self.lib.gf_kernel_time(self._h, w, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+    def set_cache_budget(self, nbytes):
+        """Infinity-Cache grouping of independent units inside sweep(); 0 turns it off"""
+        self._check(self.lib.gf_set_cache_budget(self._h, ctypes.c_int64(int(nbytes))))
+
+    def cache_groups(self):
+        g = ctypes.c_int32()
+        self._check(self.lib.gf_cache_groups(self._h, ctypes.byref(g)))
+        return g.value
 
     def set_graph(self, enable=True):
         self._check(self.lib.gf_set_graph(self._h, 1 if enable else 0))

@@ -101,3 +101,32 @@ def test_c5_gribov_batch_full_size():
     say("16^4 copy 0: F gpu", Fs[0], "oracle", Fo, "max |d Re tr U|", dtr, "same Gribov copy", same)
     if same:
         assert abs(Fs[0] - Fo) < f_orbit_tol(done[0], np.prod(d)) * Fo
+
+
+@pytest.mark.parametrize("gauge,storage", [("landau", "mixed"), ("coulomb", "mixed"), ("mag", "f64r12")])
+def test_cache_groups_give_identical_results(gauge, storage):
+    # Infinity-Cache grouping only reorders independent units: with a budget
+    # that forces several groups, every unit ends bit-identical to the
+    # ungrouped run (reprojection every 7 sweeps and the FP64-update tail
+    # included)
+    shapes = [(4, 4, 4, 4), (6, 4, 2, 4), (4, 2, 6, 2), (4, 4, 4, 4), (2, 4, 4, 6)]
+    Us = [I.smooth(d, 0.5, 7001 + k) for k, d in enumerate(shapes)]
+    outs, dones = [], []
+    for budget in (0, 1):
+        say("cache groups", gauge, storage, "budget", budget)
+        fx = fixer(shapes, gauge, storage, reunit_every=7, tail_theta=1e-8 if storage == "mixed" else 0.0)
+        fx.set_cache_budget(budget)
+        ng = fx.cache_groups()
+        nunits = sum(d[0] for d in shapes) if gauge == "coulomb" else len(shapes)
+        assert ng == (1 if budget == 0 else nunits)
+        for k, U in enumerate(Us):
+            fx.upload(k, U)
+        fx.set_overrelax(1.7)
+        st, done = fx.sweep("or", max_sweeps=3000, tol=1e-12, check_every=5)
+        assert st == 0
+        outs.append([fx.download(k) for k in range(len(shapes))])
+        dones.append(done)
+        fx.close()
+    np.testing.assert_array_equal(dones[0], dones[1])
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
