@@ -156,6 +156,7 @@ def kernel_table(gf, I, nsweeps=20):
             bps = 2 * nl * link[storage] + (2 * link[storage] if gauge == "coulomb" else 0)
             for upd in ("or", "heatbath"):
                 fx = gf.GaugeFixer([DIMS], gauge=gauge, storage=storage, reunit_every=0, tail_theta=0.0)
+                fx.set_cache_budget(0)  # one launch per half-sweep over all time-slices
                 fx.upload(0, U)
                 fx.set_overrelax(OMEGA)
                 fx.set_temperature(0.5)

@@ -144,11 +144,10 @@ __device__ __forceinline__ Q4<double> landau_heatbath(const Q4<double> &q, doubl
 
 // MAG heatbath: n(g) from von Mises-Fisher exp(kappa n.yhat), y = (F, -E, D),
 // kappa = lambda / T; then g (g3 = 0) with n(g) = n
-__device__ __forceinline__ Q4<double> mag_heatbath(double D, double E, double F, double T, const Rng &rng) {
+// u0, u1: the first two uniforms of the subgroup's draw (block 0, stream 0)
+__device__ __forceinline__ Q4<double> mag_heatbath(double D, double E, double F, double T, double u0, double u1) {
     double y0 = F, y1 = -E, y2 = D;
     const double lam = sqrt(y0 * y0 + y1 * y1 + y2 * y2);
-    double u[4];
-    rng.draw(0, 0, u);
     if (lam == 0.0) {
         y0 = 0.0;
         y1 = 0.0;
@@ -158,8 +157,8 @@ __device__ __forceinline__ Q4<double> mag_heatbath(double D, double E, double F,
         y1 /= lam;
         y2 /= lam;
     }
-    const double w = exp_icdf(lam / T, u[0]);
-    const double phi = 2.0 * M_PI * u[1];
+    const double w = exp_icdf(lam / T, u0);
+    const double phi = 2.0 * M_PI * u1;
     const double s = sqrt(fmax(0.0, 1.0 - w * w));
     double e1[3], e2[3];
     const double opz = 1.0 + y2;
@@ -430,6 +429,23 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
     } else {
         // MAG: coefficients of each subgroup from the blocks of the links
         // with the partial G applied
+        double hb_u[3][2];
+        if constexpr (UPD == gfs::UPD_HEATBATH) {
+            // the heatbath's random numbers do not depend on the links: the
+            // three subgroups' Philox chains are computed together, so they
+            // interleave instead of running back to back
+            if (wv == 0) {
+#pragma unroll
+                for (int sg = 0; sg < 3; ++sg) {
+                    Rng r2 = rng;
+                    r2.sg = (uint64_t)sg;
+                    double u[4];
+                    r2.draw(0, 0, u);
+                    hb_u[sg][0] = u[0];
+                    hb_u[sg][1] = u[1];
+                }
+            }
+        }
 #pragma unroll
         for (int sg = 0; sg < 3; ++sg) {
             const int i = (sg == 2) ? 1 : 0, jj = (sg == 0) ? 1 : 2;
@@ -461,7 +477,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
             rng.sg = (uint64_t)sg;
             Q4<CT> g;
             if constexpr (UPD == gfs::UPD_HEATBATH) {
-                if (wv == 0) g = to_T<CT>(mag_heatbath(double(D), double(E), double(F), a.T, rng));
+                if (wv == 0) g = to_T<CT>(mag_heatbath(double(D), double(E), double(F), a.T, hb_u[sg][0], hb_u[sg][1]));
                 share_from_wave0<W, GROUPS>(g, sg, grp, wv, lane);
             } else {
                 g = finish<UPD, CT>(mag_relax(D, E, F), a, rng);
