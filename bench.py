@@ -142,6 +142,73 @@ def copy_ceiling(torch, nbytes, reps=20):
     return {"bytes": 2 * nbytes, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9, "kernel": "device copy (hipMemcpyAsync)"}
 
 
+def workloads(gf, I):
+    """Wall time of two further workloads, one JSON line each, inputs resident
+    in HBM when the clock starts:
+    * 32^4 MAG, eps 0.7, seed 4001: simulated annealing T 1.5 -> 0.01 over 3000
+      steps (heatbath + 3 microcanonical sweeps each, Philox key 4002), then
+      overrelaxation omega 1.7 to theta < 1e-12, FP32-12 storage;
+    * 32 Gribov copies (8 random gauge copies each of 16^4, 24^4, 40x20^3,
+      64x32^3, eps 0.5) fixed to Landau gauge in one batched launch,
+      theta < 1e-12 per copy, FP32-12 storage."""
+    import torch
+    dims = (32, 32, 32, 32)
+    inp = torch.from_numpy(I.smooth(dims, 0.7, 4001).reshape(-1)).to("cuda:0")
+    fx = gf.GaugeFixer([dims], gauge="mag", storage="mixed", reunit_every=100, tail_theta=1e-9)
+    fx.upload(0, inp)
+    fx.set_overrelax(OMEGA)
+    fx.autotune(reps=5)
+    fx.upload(0, inp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fx.set_anneal(1.5, 0.01, 3000, nmicro=3, seed=4002)
+    fx.sweep("anneal")
+    torch.cuda.synchronize()
+    t_sa = time.perf_counter() - t0
+    F_sa, _ = fx.measure(0)
+    st, done = fx.sweep("or", max_sweeps=100000, tol=TOL, check_every=CHECK)
+    fx.reunitarise()
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    F, th = fx.measure(0)
+    fx.close()
+    print(json.dumps({"workload": "mag-32^4-eps0.7-anneal3000-T1.5to0.01-then-or", "anneal_s": round(t_sa, 3),
+                      "anneal_sweeps": 12000, "F_after_anneal": F_sa, "or_sweeps": int(done[0]), "status": st,
+                      "total_s": round(t_all, 3), "F": F, "theta": th}), flush=True)
+
+    shapes = [(16, 16, 16, 16), (24, 24, 24, 24), (40, 20, 20, 20), (64, 32, 32, 32)]
+    ncopy = 8
+    dl = [d for d in shapes for _ in range(ncopy)]
+    fx = gf.GaugeFixer(dl, gauge="landau", storage="mixed", reunit_every=100, tail_theta=1e-9)
+    ins = []
+    for li, d in enumerate(shapes):
+        base = I.smooth(d, 0.5, 5001 + li)
+        for c in range(ncopy):
+            U = base.copy()
+            I.gauge_copy(U, d, 5100 + 8 * li + c)
+            ins.append(torch.from_numpy(U.reshape(-1)).to("cuda:0"))
+    for k, x in enumerate(ins):
+        fx.upload(k, x)
+    fx.set_overrelax(OMEGA)
+    fx.autotune(reps=3)
+    for k, x in enumerate(ins):
+        fx.upload(k, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, done = fx.sweep("or", max_sweeps=100000, tol=TOL, check_every=CHECK)
+    fx.reunitarise()
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    Fs = [fx.measure(k)[0] for k in range(len(dl))]
+    groups = fx.cache_groups()
+    fx.close()
+    su = sum(int(np.prod(d)) * int(n) for d, n in zip(dl, done))
+    best = {"x".join(map(str, d)): round(max(Fs[i * ncopy:(i + 1) * ncopy]), 12) for i, d in enumerate(shapes)}
+    print(json.dumps({"workload": "landau-gribov-batch-32-copies", "status": st, "total_s": round(t_all, 3),
+                      "site_updates_per_s": su / t_all, "sweeps": done.tolist(), "cache_groups": groups,
+                      "best_F": best}), flush=True)
+
+
 def kernel_table(gf, I, nsweeps=20):
     """Half-sweep launch time and effective bandwidth of every gauge x
     storage x update on a 32^4 lattice (Coulomb: 32 time-slices of 32^3),
@@ -192,6 +259,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (scale for rocprof byte counters)")
+    ap.add_argument("--workloads", action="store_true",
+                    help="only time the annealing (32^4 MAG) and Gribov-copy batch workloads end to end")
     ap.add_argument("--kernel-table", action="store_true",
                     help="only time the half-sweep of every gauge, storage and update on 32^4 (one JSON line each)")
     ap.add_argument("--profile-sweeps", type=int, default=0,
@@ -216,6 +285,9 @@ def main():
         return
     if args.kernel_table:
         kernel_table(gf, I)
+        return
+    if args.workloads:
+        workloads(gf, I)
         return
     if args.profile_sweeps:
         # a fixed number of OR sweeps of seed 2001 in the benchmark's launch
