@@ -92,7 +92,6 @@ struct gf_ctx {
     std::vector<Pending> ev_pending;
     double t_sum_ms[2] = {0.0, 0.0};
     int64_t t_count[2] = {0, 0};
-    double t_min_ms[2] = {1e300, 1e300};
 
     bool use_graph = true;
     GraphCache graph;
@@ -315,9 +314,7 @@ int check_unbound(gf_ctx *h) {
 // bytes a unit's sweeps touch: 8 link planes over its half-sites (Coulomb:
 // 6 spatial planes and the 2 accumulator planes)
 int64_t unit_bytes(const gf_ctx *h, int u) {
-    const int st = st_code(h->storage);
-    const int64_t link = (st == gfs::ST_F32R12) ? 48 : (st == gfs::ST_F64R12 ? 96 : 144);
-    return 8 * (int64_t)h->units[u].n * link;
+    return 8 * (int64_t)h->units[u].n * nchunks(h->storage) * 16;
 }
 
 void build_groups(gf_ctx *h) {
@@ -384,7 +381,6 @@ int drain_timing(gf_ctx *h) {
         HIPCHK(h, hipEventElapsedTime(&ms, p.e0, p.e1));
         h->t_sum_ms[p.ctd] += ms;
         h->t_count[p.ctd] += 1;
-        h->t_min_ms[p.ctd] = std::min(h->t_min_ms[p.ctd], (double)ms);
         h->ev_pool.push_back(p.e0);
         h->ev_pool.push_back(p.e1);
     }
@@ -1185,7 +1181,6 @@ int gf_set_timing(gf_handle h, int every) {
     h->launch_seq = 0;
     h->t_sum_ms[0] = h->t_sum_ms[1] = 0.0;
     h->t_count[0] = h->t_count[1] = 0;
-    h->t_min_ms[0] = h->t_min_ms[1] = 1e300;
     return GF_OK;
 }
 
