@@ -130,3 +130,4 @@ def test_cache_groups_give_identical_results(gauge, storage):
     np.testing.assert_array_equal(dones[0], dones[1])
     for a, b in zip(outs[0], outs[1]):
         np.testing.assert_array_equal(a, b)
+
