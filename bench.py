@@ -143,11 +143,13 @@ def copy_ceiling(torch, nbytes, reps=20):
 
 
 def workloads(gf, I):
-    """Wall time of two further workloads, one JSON line each, inputs resident
-    in HBM when the clock starts:
+    """Wall time of further workloads, one JSON line each, inputs resident in
+    HBM when the clock starts:
     * 32^4 MAG, eps 0.7, seed 4001: simulated annealing T 1.5 -> 0.01 over 3000
       steps (heatbath + 3 microcanonical sweeps each, Philox key 4002), then
       overrelaxation omega 1.7 to theta < 1e-12, FP32-12 storage;
+    * 64^3 x 256 Coulomb: time per sweep (checks every 20 sweeps included)
+      without and with Infinity-Cache groups;
     * 32 Gribov copies (8 random gauge copies each of 16^4, 24^4, 40x20^3,
       64x32^3, eps 0.5) fixed to Landau gauge in one batched launch,
       theta < 1e-12 per copy, FP32-12 storage."""
@@ -175,6 +177,32 @@ def workloads(gf, I):
     print(json.dumps({"workload": "mag-32^4-eps0.7-anneal3000-T1.5to0.01-then-or", "anneal_s": round(t_sa, 3),
                       "anneal_sweeps": 12000, "F_after_anneal": F_sa, "or_sweeps": int(done[0]), "status": st,
                       "total_s": round(t_all, 3), "F": F, "theta": th}), flush=True)
+
+    # 64^3 x 256 Coulomb sweep throughput: 16 generated time-slices repeated
+    # 16 times (the cost of a sweep does not depend on the link values), 40
+    # sweeps without and with Infinity-Cache groups
+    dims = (256, 64, 64, 64)
+    vs = 64 ** 3
+    slab = torch.from_numpy(I.smooth(dims, 0.5, 3001, t0=0, nt=16).reshape(-1)).to("cuda:0")
+    fx = gf.GaugeFixer([dims], gauge="coulomb", storage="mixed", reunit_every=100, tail_theta=1e-9)
+    for t0 in range(0, 256, 16):
+        fx.upload(0, slab, t0=t0, nt=16)
+    del slab
+    fx.set_overrelax(OMEGA)
+    fx.autotune(reps=2)
+    out = {"workload": "coulomb-64^3x256-sweep-throughput"}
+    for budget in (0, 224 << 20):
+        fx.set_cache_budget(budget)
+        fx.sweep("or", max_sweeps=CHECK, tol=0.0, check_every=CHECK)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fx.sweep("or", max_sweeps=2 * CHECK, tol=0.0, check_every=CHECK)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / (2 * CHECK) * 1e3
+        out["groups_%d" % fx.cache_groups()] = {"ms_per_sweep": round(ms, 3),
+                                                 "GBs": round(672 * 256 * vs / (ms * 1e-3) / 1e9)}
+    fx.close()
+    print(json.dumps(out), flush=True)
 
     shapes = [(16, 16, 16, 16), (24, 24, 24, 24), (40, 20, 20, 20), (64, 32, 32, 32)]
     ncopy = 8
