@@ -18,7 +18,7 @@ import pytest
 
 import oracle as O
 from paper_1212_5221_amd import inputs as I
-from tests.test_gpu_parity import fixer, say
+from tests.test_gpu_parity import f_orbit_tol, fixer, say
 
 pytestmark = pytest.mark.gpu
 
@@ -205,3 +205,19 @@ def test_c4_mag_anneal_full_size():
     Fo, tho = O.measure(out, dims, "mag")
     # the final FP32 rounding of the reprojected links moves theta by ~1e-12
     assert abs(Fo - F) < 1e-9 and tho < 5e-12
+    # the overrelaxation stage against the oracle's, from the same annealed
+    # (FP32-rounded) state: same even half-sweep first, then sweeps to
+    # theta < 1e-12 in FP64.  F agrees within the storage-rounding bound (MAG's
+    # F averages |U_ii|^2, twice the relative rounding of Re tr U) unless the
+    # runs end in different copies (Re tr U per link tells).
+    ref = annealed.copy()
+    O.halfsweep(ref, dims, "mag", "or", 0, omega=1.7)
+    r = O.run(ref, dims, "mag", "or", omega=1.7, max_sweeps=100000, tol=1e-12, check_every=10)
+    Fr = O.measure(ref, dims, "mag")[0]
+    dtr = np.max(np.abs((out[..., 0, 0, 0] + out[..., 1, 1, 0] + out[..., 2, 2, 0]) -
+                        (ref[..., 0, 0, 0] + ref[..., 1, 1, 0] + ref[..., 2, 2, 0])))
+    say("OR stage: oracle sweeps", r.sweeps_done.tolist(), "F", Fr, "gpu F", F, "rel", abs(F - Fr) / Fr,
+        "max |d Re tr U|", dtr)
+    assert r.status == 0
+    if dtr < 1e-3:
+        assert abs(F - Fr) < 2 * f_orbit_tol(done[0], np.prod(dims)) * Fr

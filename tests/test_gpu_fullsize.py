@@ -8,8 +8,8 @@ in the launch configuration bench.py times (autotuned waves per site group).
   measured by the oracle on the downloaded links, gauge invariants unchanged,
   unitarity after the final FP64 reprojection) and F against the oracle's
   converged F stored in tests/golden (written by a script calling only the
-  oracle), within the bound of f_orbit_tol unless the two runs ended in
-  different Gribov copies.
+  oracle), relative 1e-9 unless the two runs ended in different Gribov
+  copies.
 """
 import json
 import os
@@ -20,7 +20,7 @@ import pytest
 
 import oracle as O
 from paper_1212_5221_amd import inputs as I
-from tests.test_gpu_parity import f32_round, f_orbit_tol, say
+from tests.test_gpu_parity import f32_round, say
 
 pytestmark = pytest.mark.gpu
 
@@ -108,6 +108,8 @@ def test_c2_full_fix_properties():
             same_copy = all(abs((out[s, m, 0, 0, 0] + out[s, m, 1, 1, 0] + out[s, m, 2, 2, 0]) - v) < 1e-5
                             for s, m, v in g["retrace_samples"])
             if same_copy:
-                assert rel < f_orbit_tol(done[0], np.prod(DIMS))
+                # the 1e-9 target for this workload; the rounding-walk bound
+                # f_orbit_tol (9e-9 here) would allow more
+                assert rel < 1e-9
             else:
                 pytest.skip("mixed and FP64 runs ended in different Gribov copies (F differs by %.2e)" % rel)
