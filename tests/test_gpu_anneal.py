@@ -209,15 +209,19 @@ def test_c4_mag_anneal_full_size():
     # (FP32-rounded) state: same even half-sweep first, then sweeps to
     # theta < 1e-12 in FP64.  F agrees within the storage-rounding bound (MAG's
     # F averages |U_ii|^2, twice the relative rounding of Re tr U) unless the
-    # runs end in different copies (Re tr U per link tells).
+    # runs end in different copies.  MAG leaves a local U(1) x U(1) freedom
+    # (diagonal phases), which changes Re tr U but not the per-link
+    # sum_i |U_ii|^2: within one copy the two fixes differ in it by the
+    # residual of the stopping tolerance (~1e-3 for MAG's slow modes),
+    # distinct copies by O(0.1).
     ref = annealed.copy()
     O.halfsweep(ref, dims, "mag", "or", 0, omega=1.7)
     r = O.run(ref, dims, "mag", "or", omega=1.7, max_sweeps=100000, tol=1e-12, check_every=10)
     Fr = O.measure(ref, dims, "mag")[0]
-    dtr = np.max(np.abs((out[..., 0, 0, 0] + out[..., 1, 1, 0] + out[..., 2, 2, 0]) -
-                        (ref[..., 0, 0, 0] + ref[..., 1, 1, 0] + ref[..., 2, 2, 0])))
+    dia = lambda W: sum(W[..., i, i, 0] ** 2 + W[..., i, i, 1] ** 2 for i in range(3))
+    ddia = float(np.max(np.abs(dia(out) - dia(ref))))
     say("OR stage: oracle sweeps", r.sweeps_done.tolist(), "F", Fr, "gpu F", F, "rel", abs(F - Fr) / Fr,
-        "max |d Re tr U|", dtr)
+        "max |d sum |U_ii|^2|", ddia)
     assert r.status == 0
-    if dtr < 1e-3:
+    if ddia < 2e-2:
         assert abs(F - Fr) < 2 * f_orbit_tol(done[0], np.prod(dims)) * Fr

@@ -92,12 +92,11 @@ def test_c5_gribov_batch_full_size():
     fx.close()
     # Re tr U(x) per link is invariant under the global transformations that
     # the Landau condition leaves free; two runs in the same Gribov copy agree
-    # on it up to the residual of the stopping tolerance (about
-    # sqrt(theta) / lowest lattice Laplacian eigenvalue, ~1e-5 here) while
-    # distinct copies differ by far more
+    # on it up to the residual of the stopping tolerance (the slowest modes:
+    # up to ~1e-4) while distinct copies differ by O(0.1)
     dtr = np.max(np.abs((out[..., 0, 0, 0] + out[..., 1, 1, 0] + out[..., 2, 2, 0]) -
                         (U[..., 0, 0, 0] + U[..., 1, 1, 0] + U[..., 2, 2, 0])))
-    same = dtr < 1e-3
+    same = dtr < 1e-2
     say("16^4 copy 0: F gpu", Fs[0], "oracle", Fo, "max |d Re tr U|", dtr, "same Gribov copy", same)
     if same:
         assert abs(Fs[0] - Fo) < f_orbit_tol(done[0], np.prod(d)) * Fo

@@ -104,9 +104,14 @@ def test_c2_full_fix_properties():
         if g:
             rel = abs(F - g["F"]) / g["F"]
             say("F vs oracle F", F, g["F"], "rel", rel)
-            # gauge-invariant per-link field: same Gribov copy?
-            same_copy = all(abs((out[s, m, 0, 0, 0] + out[s, m, 1, 1, 0] + out[s, m, 2, 2, 0]) - v) < 1e-5
-                            for s, m, v in g["retrace_samples"])
+            # Re tr U per link (invariant under the global transformations the
+            # Landau condition leaves free): within one Gribov copy the two
+            # fixes differ by the residual of the stopping tolerance (up to
+            # ~1e-4 here), distinct copies by O(0.1)
+            dtr = max(abs((out[s, m, 0, 0, 0] + out[s, m, 1, 1, 0] + out[s, m, 2, 2, 0]) - v)
+                      for s, m, v in g["retrace_samples"])
+            say("max |d Re tr U| over the sampled links", dtr)
+            same_copy = dtr < 1e-2
             if same_copy:
                 # the 1e-9 target for this workload; the rounding-walk bound
                 # f_orbit_tol (9e-9 here) would allow more
