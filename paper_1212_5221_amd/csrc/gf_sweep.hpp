@@ -250,36 +250,79 @@ __device__ __forceinline__ void share_from_wave0(Q4<T> &g, int sg, int grp, int 
 
 // ---------------------------------------------------------------- MAG blocks
 // block (i,j) of G U (forward link) and of U G^dag (backward link)
+// G is the product of the subgroup elements of the earlier subgroups: the
+// identity before subgroup 0, and nontrivial only in its (0,1) block before
+// subgroup 1.  The block products below skip those known zeros, which the
+// compiler has to keep (x * 0 is not 0 for x = NaN or -0).
 template <typename T>
-__device__ __forceinline__ void mag_block_fwd(const M3<T> &G, const M3<T> &U, int i, int j, T &D, T &E, T &F) {
-    cx<T> a = cmk(T(0), T(0)), b = a, c = a, d = a;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        a = cmac(a, G.e[i][k], U.e[k][i]);
-        b = cmac(b, G.e[i][k], U.e[k][j]);
-        c = cmac(c, G.e[j][k], U.e[k][i]);
-        d = cmac(d, G.e[j][k], U.e[k][j]);
-    }
+__device__ __forceinline__ void mag_coef_add(cx<T> a, cx<T> b, cx<T> c, cx<T> d, bool fwd, T &D, T &E, T &F) {
     D += T(0.5) * (cnorm2(a) + cnorm2(d) - cnorm2(b) - cnorm2(c));
-    const cx<T> w = csub(cmulc(a, c), cmulc(b, d));  // a c* - b d*
+    const cx<T> w = fwd ? csub(cmulc(a, c), cmulc(b, d))   // a c* - b d*
+                        : csub(cmulc(b, a), cmulc(d, c));  // a* b - d c*
     F += w.re;
     E += w.im;
 }
 
-template <typename T>
-__device__ __forceinline__ void mag_block_bwd(const M3<T> &G, const M3<T> &U, int i, int j, T &D, T &E, T &F) {
-    cx<T> a = cmk(T(0), T(0)), b = a, c = a, d = a;
+// block (i,j) of G U (forward link), subgroup SG
+template <int SG, typename T>
+__device__ __forceinline__ void mag_block_fwd(const M3<T> &G, const M3<T> &U, T &D, T &E, T &F) {
+    constexpr int i = (SG == 2) ? 1 : 0, j = (SG == 0) ? 1 : 2;
+    cx<T> a, b, c, d;
+    if constexpr (SG == 0) {
+        a = U.e[0][0];
+        b = U.e[0][1];
+        c = U.e[1][0];
+        d = U.e[1][1];
+    } else if constexpr (SG == 1) {
+        a = cmac(cmul(G.e[0][0], U.e[0][0]), G.e[0][1], U.e[1][0]);
+        b = cmac(cmul(G.e[0][0], U.e[0][2]), G.e[0][1], U.e[1][2]);
+        c = U.e[2][0];
+        d = U.e[2][2];
+    } else {
+        a = cmul(G.e[i][0], U.e[0][i]);
+        b = cmul(G.e[i][0], U.e[0][j]);
+        c = cmul(G.e[j][0], U.e[0][i]);
+        d = cmul(G.e[j][0], U.e[0][j]);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        a = cmacc(a, U.e[i][k], G.e[i][k]);
-        b = cmacc(b, U.e[i][k], G.e[j][k]);
-        c = cmacc(c, U.e[j][k], G.e[i][k]);
-        d = cmacc(d, U.e[j][k], G.e[j][k]);
+        for (int k = 1; k < 3; ++k) {
+            a = cmac(a, G.e[i][k], U.e[k][i]);
+            b = cmac(b, G.e[i][k], U.e[k][j]);
+            c = cmac(c, G.e[j][k], U.e[k][i]);
+            d = cmac(d, G.e[j][k], U.e[k][j]);
+        }
     }
-    D += T(0.5) * (cnorm2(a) + cnorm2(d) - cnorm2(b) - cnorm2(c));
-    const cx<T> w = csub(cmulc(b, a), cmulc(d, c));  // a* b - d c*
-    F += w.re;
-    E += w.im;
+    mag_coef_add(a, b, c, d, true, D, E, F);
+}
+
+// block (i,j) of U G^dag (backward link), subgroup SG
+template <int SG, typename T>
+__device__ __forceinline__ void mag_block_bwd(const M3<T> &G, const M3<T> &U, T &D, T &E, T &F) {
+    constexpr int i = (SG == 2) ? 1 : 0, j = (SG == 0) ? 1 : 2;
+    cx<T> a, b, c, d;
+    if constexpr (SG == 0) {
+        a = U.e[0][0];
+        b = U.e[0][1];
+        c = U.e[1][0];
+        d = U.e[1][1];
+    } else if constexpr (SG == 1) {
+        a = cmacc(cmulc(U.e[0][0], G.e[0][0]), U.e[0][1], G.e[0][1]);
+        b = U.e[0][2];
+        c = cmacc(cmulc(U.e[2][0], G.e[0][0]), U.e[2][1], G.e[0][1]);
+        d = U.e[2][2];
+    } else {
+        a = cmulc(U.e[i][0], G.e[i][0]);
+        b = cmulc(U.e[i][0], G.e[j][0]);
+        c = cmulc(U.e[j][0], G.e[i][0]);
+        d = cmulc(U.e[j][0], G.e[j][0]);
+#pragma unroll
+        for (int k = 1; k < 3; ++k) {
+            a = cmacc(a, U.e[i][k], G.e[i][k]);
+            b = cmacc(b, U.e[i][k], G.e[j][k]);
+            c = cmacc(c, U.e[j][k], G.e[i][k]);
+            d = cmacc(d, U.e[j][k], G.e[j][k]);
+        }
+    }
+    mag_coef_add(a, b, c, d, false, D, E, F);
 }
 
 // ---------------------------------------------------------------- apply
@@ -455,10 +498,21 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
                 const int l = wv * LPW + q;
                 M3<CT> m;
                 expand<ST, CT>(r[q], m);
-                if (l < NDIR)
-                    mag_block_fwd(G, m, i, jj, D, E, F);
-                else
-                    mag_block_bwd(G, m, i, jj, D, E, F);
+                if (l < NDIR) {
+                    if (sg == 0)
+                        mag_block_fwd<0>(G, m, D, E, F);
+                    else if (sg == 1)
+                        mag_block_fwd<1>(G, m, D, E, F);
+                    else
+                        mag_block_fwd<2>(G, m, D, E, F);
+                } else {
+                    if (sg == 0)
+                        mag_block_bwd<0>(G, m, D, E, F);
+                    else if (sg == 1)
+                        mag_block_bwd<1>(G, m, D, E, F);
+                    else
+                        mag_block_bwd<2>(G, m, D, E, F);
+                }
             }
             if constexpr (W > 1) {
                 __shared__ CT shm[3][GROUPS][W][3][64];
