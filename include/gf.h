@@ -189,9 +189,11 @@ int gf_set_sweep_index(gf_handle h, int32_t inst, uint64_t index);
    sites, each holding 8/waves_per_site (Coulomb 6/waves_per_site) of the
    adjacent links, with the partial sums exchanged through LDS (the
    eight-threads-per-site idea of Sec. 4.3 at wavefront granularity): 1, 2 or
-   4 (Coulomb 1 or 2); 0 = library default.  Applies to the FP32-update and
-   the FP64-update kernels where the variant exists.  block: threads per
-   workgroup, 256 (or 0).  GF_E_INVALID for an unavailable variant. */
+   4 (Coulomb 1 or 2); 0 = library default (FP32 update 1, FP64 update 4
+   where available; heatbath 1 on FP32 storage, 2 on FP64-12, 4 on FP64-18).
+   Applies to the FP32-update, the FP64-update and the heatbath kernels where
+   the variant exists.  block: threads per workgroup, 256 (or 0).
+   GF_E_INVALID for an unavailable variant. */
 int gf_set_launch(gf_handle h, int waves_per_site, int block);
 
 /* Time the available variants of the OR half-sweep on the bound

@@ -63,17 +63,18 @@ struct gf_ctx {
     size_t ws_bytes = 0;
 
     // workspace layout (byte offsets)
-    size_t off_inst = 0, off_unit = 0, off_tiles[2] = {0, 0}, off_mtiles = 0, off_partial = 0, off_res = 0;
+    size_t off_inst = 0, off_unit = 0, off_tiles[3] = {0, 0, 0}, off_mtiles = 0, off_partial = 0, off_res = 0;
     size_t off_active = 0, off_fp64 = 0, off_sweeps = 0, off_sweepix = 0, off_status = 0, off_stage = 0;
     size_t stage_bytes = 0, need_bytes = 0;
     int nunits = 0, nmtiles = 0;
     int64_t max_tiles = 0;
     std::vector<gfs::UnitDev> units;
 
-    // launch configuration per compute precision of the update (0 FP32, 1 FP64):
-    // wavefronts per group of 64 sites and the matching sweep tile tables
-    int W[2] = {1, 1};
-    int ntiles[2] = {0, 0};
+    // launch configuration per tile table: 0 FP32 update, 1 FP64 update, 2
+    // heatbath (FP64): wavefronts per group of 64 sites and the matching
+    // sweep tile tables
+    int W[3] = {1, 1, 1};
+    int ntiles[3] = {0, 0, 0};
     int force_ctd = -1;  // autotuning: time one precision only
 
     // host readback (pinned)
@@ -101,7 +102,7 @@ struct gf_ctx {
     // every unit's sequence of sweeps is unchanged)
     int64_t cache_budget = (int64_t)224 << 20;
     std::vector<int> grp_u0;         // group g = units [grp_u0[g], grp_u0[g + 1])
-    std::vector<int32_t> tile_u0[2]; // per compute precision: first tile of each unit (+ end)
+    std::vector<int32_t> tile_u0[3]; // per tile table: first tile of each unit (+ end)
 
     // from the last check: active units, of which in the FP64 tail
     int n_active = 0, n_tail = 0;
@@ -229,7 +230,7 @@ void plan_layout(gf_ctx *h) {
     off += align256(sizeof(gfs::InstDev) * h->inst.size());
     h->off_unit = off;
     off += align256(sizeof(gfs::UnitDev) * h->nunits);
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < 3; ++v) {
         h->off_tiles[v] = off;
         off += align256(sizeof(gfs::Tile) * (size_t)h->max_tiles);
     }
@@ -270,32 +271,39 @@ gfs::InstDev inst_dev(const InstHost &I) {
     return d;
 }
 
-int build_tiles(gf_ctx *h, int ctd, int W) {
+// sweep tile table `tab` (0 FP32 update, 1 FP64 update, 2 heatbath) for W
+// wavefronts per group of 64 sites
+int build_tiles(gf_ctx *h, int tab, int W) {
     const int spb = gfl::SWEEP_THREADS / W;
     std::vector<gfs::Tile> t;
-    h->tile_u0[ctd].assign(h->nunits + 1, 0);
+    h->tile_u0[tab].assign(h->nunits + 1, 0);
     for (int u = 0; u < h->nunits; ++u) {
-        h->tile_u0[ctd][u] = (int32_t)t.size();
+        h->tile_u0[tab][u] = (int32_t)t.size();
         for (int32_t j = 0; j < h->units[u].n; j += spb) t.push_back({u, j});
     }
-    h->tile_u0[ctd][h->nunits] = (int32_t)t.size();
+    h->tile_u0[tab][h->nunits] = (int32_t)t.size();
     if ((int64_t)t.size() > h->max_tiles) return fail(h, GF_E_INVALID, "tile table overflow");
-    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_tiles[ctd], t.data(), sizeof(gfs::Tile) * t.size(), hipMemcpyHostToDevice,
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_tiles[tab], t.data(), sizeof(gfs::Tile) * t.size(), hipMemcpyHostToDevice,
                              h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    h->ntiles[ctd] = (int)t.size();
-    h->W[ctd] = W;
+    h->ntiles[tab] = (int)t.size();
+    h->W[tab] = W;
     h->graph.clear();
     return GF_OK;
 }
 
 // default wavefronts per site group: FP32 update 1, FP64 update the largest
-// available of 4, 2, 1 (fewer links per wavefront, more waves in flight)
-int default_W_for(const gf_ctx *h, int ctd) {
+// available of 4, 2, 1 (fewer links per wavefront, more waves in flight);
+// heatbath (table 2, measured at 32^4): 1 on FP32 storage, 2 on FP64-12, 4
+// on FP64-18 where available
+int default_W_for(const gf_ctx *h, int tab) {
     const int st = st_code(h->storage);
-    if (ctd == 0) return 1;
-    for (int W = 4; W >= 1; W /= 2)
-        if (gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, 1, W)) return W;
+    if (tab == 0) return 1;
+    const int upd = (tab == 2) ? gfs::UPD_HEATBATH : gfs::UPD_OR;
+    int first = 4;
+    if (tab == 2) first = (st == gfs::ST_F32R12) ? 1 : (st == gfs::ST_F64R12 ? 2 : 4);
+    for (int W = first; W >= 1; W /= 2)
+        if (gfl::sweep_kernel(h->gauge, upd, st, 1, W)) return W;
     return 1;
 }
 
@@ -335,16 +343,16 @@ void build_groups(gf_ctx *h) {
 int ngroups(const gf_ctx *h) { return (int)h->grp_u0.size() - 1; }
 
 // grp < 0: every tile; else the tiles of group grp
-gfs::SweepArgs sweep_args(gf_ctx *h, int parity, int fp64_select, double T, int ctd, int sweep_off, int grp,
+gfs::SweepArgs sweep_args(gf_ctx *h, int parity, int fp64_select, double T, int tab, int sweep_off, int grp,
                           int *ntiles) {
     gfs::SweepArgs a;
     a.ws = h->ws;
     a.inst = wsp<gfs::InstDev>(h, h->off_inst);
     a.unit = wsp<gfs::UnitDev>(h, h->off_unit);
-    a.tiles = wsp<gfs::Tile>(h, h->off_tiles[ctd]);
-    *ntiles = h->ntiles[ctd];
+    a.tiles = wsp<gfs::Tile>(h, h->off_tiles[tab]);
+    *ntiles = h->ntiles[tab];
     if (grp >= 0) {
-        const int32_t t0 = h->tile_u0[ctd][h->grp_u0[grp]], t1 = h->tile_u0[ctd][h->grp_u0[grp + 1]];
+        const int32_t t0 = h->tile_u0[tab][h->grp_u0[grp]], t1 = h->tile_u0[tab][h->grp_u0[grp + 1]];
         a.tiles += t0;
         *ntiles = t1 - t0;
     }
@@ -394,34 +402,37 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
     const bool mixed = (h->storage == GF_MIXED_F32_R12);
     const bool hb = (upd == gfs::UPD_HEATBATH || upd == gfs::UPD_SR);
     // compute precision: FP64 storage -> double; mixed -> float (+ double tail)
+    // ctd: compute precision of the update (0 FP32, 1 FP64); tab: tile table
     struct L {
-        int ctd, sel;
+        int ctd, sel, tab;
     } launches[2];
     int nl = 0;
     if (h->force_ctd >= 0) {
-        launches[nl++] = {h->force_ctd, -1};
+        launches[nl++] = {h->force_ctd, -1, h->force_ctd};
+    } else if (upd == gfs::UPD_HEATBATH) {
+        launches[nl++] = {1, -1, 2};
     } else if (!mixed || hb) {
-        launches[nl++] = {1, -1};
+        launches[nl++] = {1, -1, 1};
     } else if (h->tail_theta > 0.0) {
         // only the variants some active unit needs (counts of the last check)
         if (h->n_tail == 0)
-            launches[nl++] = {0, -1};
+            launches[nl++] = {0, -1, 0};
         else if (h->n_tail >= h->n_active)
-            launches[nl++] = {1, -1};
+            launches[nl++] = {1, -1, 1};
         else {
-            launches[nl++] = {0, 0};
-            launches[nl++] = {1, 1};
+            launches[nl++] = {0, 0, 0};
+            launches[nl++] = {1, 1, 1};
         }
     } else {
-        launches[nl++] = {0, -1};
+        launches[nl++] = {0, -1, 0};
     }
     for (int k = 0; k < nl; ++k) {
-        const int ctd = launches[k].ctd;
-        gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, st, ctd, h->W[ctd]);
+        const int ctd = launches[k].ctd, tab = launches[k].tab;
+        gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, st, ctd, h->W[tab]);
         if (!fn) return fail(h, GF_E_INVALID, "no kernel variant for gauge %d update %d storage %d W %d", h->gauge, upd,
-                             h->storage, h->W[ctd]);
+                             h->storage, h->W[tab]);
         int nt = 0;
-        gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T, ctd, sweep_off, grp, &nt);
+        gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T, tab, sweep_off, grp, &nt);
         if (nt <= 0) continue;
         bool tm = false;
         if (h->timing && !capturing) tm = (h->launch_seq++ % (uint64_t)h->time_every) == 0;
@@ -552,7 +563,7 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
     if (h->storage == GF_MIXED_F32_R12 && h->tail_theta > 0.0)
         tailkey = (h->n_tail == 0) ? 1 : (h->n_tail >= h->n_active ? 2 : 3);
     GraphCache &g = h->graph;
-    const int wkey = h->W[0] * 16 + h->W[1];
+    const int wkey = (h->W[0] * 16 + h->W[1]) * 16 + h->W[2];
     if (!(g.exec && g.key_upd == upd && g.key_n == n && g.key_W == wkey && g.key_tail == tailkey)) {
         g.clear();
         if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
@@ -744,6 +755,7 @@ int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes) {
     build_groups(h);
     rc = build_tiles(h, 0, default_W_for(h, 0));
     if (rc == GF_OK) rc = build_tiles(h, 1, default_W_for(h, 1));
+    if (rc == GF_OK) rc = build_tiles(h, 2, default_W_for(h, 2));
     if (rc) {
         h->bound = false;
         return rc;
@@ -1083,10 +1095,11 @@ int gf_set_launch(gf_handle h, int lanes_per_site, int block) {
     if (block != 0 && block != gfl::SWEEP_THREADS) return fail(h, GF_E_INVALID, "block %d not available", block);
     const int st = st_code(h->storage);
     int set = 0;
-    for (int ctd = 0; ctd < 2; ++ctd) {
-        const int W = lanes_per_site == 0 ? default_W_for(h, ctd) : lanes_per_site;
-        if (!gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, ctd, W)) continue;
-        rc = build_tiles(h, ctd, W);
+    for (int tab = 0; tab < 3; ++tab) {
+        const int W = lanes_per_site == 0 ? default_W_for(h, tab) : lanes_per_site;
+        const int upd = (tab == 2) ? gfs::UPD_HEATBATH : gfs::UPD_OR;
+        if (!gfl::sweep_kernel(h->gauge, upd, st, tab == 0 ? 0 : 1, W)) continue;
+        rc = build_tiles(h, tab, W);
         if (rc) return rc;
         ++set;
     }
