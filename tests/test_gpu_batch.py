@@ -130,3 +130,28 @@ def test_cache_groups_give_identical_results(gauge, storage):
     for a, b in zip(outs[0], outs[1]):
         np.testing.assert_array_equal(a, b)
 
+
+
+@pytest.mark.parametrize("gauge", ["landau", "coulomb"])
+def test_graph_replays_match_plain_launches(gauge):
+    # chunks of sweeps are captured once in a HIP graph and replayed, with
+    # the checks' own launches and host reads in between; every replay must
+    # do exactly what the plain launches do
+    shapes = [(4, 4, 4, 4), (6, 4, 2, 4)]
+    Us = [I.smooth(d, 0.5, 7201 + k) for k, d in enumerate(shapes)]
+    outs, dones = [], []
+    for graph in (False, True):
+        say("graph", graph, gauge)
+        fx = fixer(shapes, gauge, "mixed", reunit_every=10, tail_theta=1e-9)
+        fx.set_graph(graph)
+        for k, U in enumerate(Us):
+            fx.upload(k, U)
+        fx.set_overrelax(1.7)
+        st, done = fx.sweep("or", max_sweeps=3000, tol=1e-12, check_every=5)
+        assert st == 0
+        outs.append([fx.download(k) for k in range(len(shapes))])
+        dones.append(done)
+        fx.close()
+    np.testing.assert_array_equal(dones[0], dones[1])
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
