@@ -142,12 +142,14 @@ def test_graph_replays_match_plain_launches(gauge):
     outs, dones = [], []
     for graph in (False, True):
         say("graph", graph, gauge)
-        fx = fixer(shapes, gauge, "mixed", reunit_every=10, tail_theta=1e-9)
+        # a graph holds a chunk of check_every sweeps; reprojection every 5
+        # sweeps falls inside it at fixed positions
+        fx = fixer(shapes, gauge, "mixed", reunit_every=5, tail_theta=1e-9)
         fx.set_graph(graph)
         for k, U in enumerate(Us):
             fx.upload(k, U)
         fx.set_overrelax(1.7)
-        st, done = fx.sweep("or", max_sweeps=3000, tol=1e-12, check_every=5)
+        st, done = fx.sweep("or", max_sweeps=3000, tol=1e-12, check_every=10)
         assert st == 0
         outs.append([fx.download(k) for k in range(len(shapes))])
         dones.append(done)
