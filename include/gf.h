@@ -206,10 +206,11 @@ int gf_set_launch(gf_handle h, int waves_per_site, int block);
    choice. */
 int gf_autotune(gf_handle h, int reps, int *waves_per_site, int *block);
 
-/* Kernel timing: every: 0 off; n >= 1 brackets every n-th half-sweep launch
-   with HIP events recorded by the launch itself on the handle's stream
-   (n = 1: every launch; a larger odd n samples both parities at a fraction of
-   the event overhead).  HIP graphs are not used while timing is on.
+/* Kernel timing: every: 0 off; n >= 1 times half-sweep launches with HIP
+   events that the launch itself records on the handle's stream.  Inside
+   gf_sweep, the launches of every n-th chunk of check_every sweeps are timed
+   (plain launches; the other chunks replay their HIP graphs as usual);
+   elsewhere every launch is timed.  n = 1: every launch, no graphs.
    GF_E_INVALID for every < 0.
    gf_kernel_time returns the number of timed half-sweep launches and their
    mean duration in milliseconds since timing was last set; which: 0 all
@@ -233,7 +234,10 @@ int gf_kernel_time(gf_handle h, int which, int64_t *launches, double *mean_ms);
 int gf_set_cache_budget(gf_handle h, int64_t bytes);
 int gf_cache_groups(gf_handle h, int32_t *groups);
 
-/* HIP graph capture of the sweep loop between checks (1 = on, default). */
+/* HIP graph capture of the sweep loop between checks (1 = on, default):
+   each chunk of check_every sweeps is captured once per launch pattern
+   (update, waves per site group, FP64-update variants, position relative to
+   the reprojection interval) and replayed. */
 int gf_set_graph(gf_handle h, int enable);
 
 #ifdef __cplusplus

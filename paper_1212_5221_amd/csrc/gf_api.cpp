@@ -26,16 +26,25 @@ struct InstHost {
     int64_t links_off, g_off;
 };
 
-struct GraphCache {
+// Graphs of chunks of sweeps, one per launch pattern: update, chunk length,
+// waves per site group, FP64-update variants in use, and the position of
+// the chunk relative to the reprojection interval (which sweeps of the chunk
+// reproject).  Every setter that changes a kernel argument clears it.
+struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    int key_upd = -1, key_n = -1, key_W = -1, key_tail = -1;
+    int key_upd = -1, key_n = -1, key_W = -1, key_tail = -1, key_r = -1;
+};
+
+struct GraphCache {
+    static constexpr size_t kMax = 8;
+    std::vector<GraphEntry> e;
     void clear() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
-        key_upd = key_n = key_W = key_tail = -1;
+        for (auto &g : e) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+        }
+        e.clear();
     }
 };
 
@@ -81,10 +90,13 @@ struct gf_ctx {
     int32_t *hstat = nullptr;
     double *hres = nullptr;
 
-    // timing: every time_every-th half-sweep launch is bracketed by events
+    // timing: inside gf_sweep every time_every-th chunk runs plain launches,
+    // each bracketed by events (time_now), the others replay graphs;
+    // elsewhere every launch is timed
     bool timing = false;
     int time_every = 1;
-    uint64_t launch_seq = 0;
+    uint64_t chunk_seq = 0;
+    bool time_now = true;
     std::vector<hipEvent_t> ev_pool;
     struct Pending {
         hipEvent_t e0, e1;
@@ -434,8 +446,7 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
         int nt = 0;
         gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T, tab, sweep_off, grp, &nt);
         if (nt <= 0) continue;
-        bool tm = false;
-        if (h->timing && !capturing) tm = (h->launch_seq++ % (uint64_t)h->time_every) == 0;
+        const bool tm = h->timing && !capturing && h->time_now;
         if (tm) {
             // the launch itself records its start and stop events
             hipEvent_t e0 = take_event(h), e1 = take_event(h);
@@ -550,26 +561,33 @@ int coulomb_finish(gf_ctx *h) {
 // run `n` sweeps starting at sweep count k0 (of this gf_sweep call)
 int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
     const int R = h->reunit_every;
-    // a graph replays a chunk of n sweeps; reprojection points must not depend
-    // on k0, so graphs are used only when no reprojection falls inside or
-    // when R divides the chunk boundary pattern identically
-    const bool graph_ok = h->use_graph && !h->timing && chunk_is_full && (R == 0 || (n % R == 0 && k0 % R == 0));
+    // with timing on, every time_every-th chunk is a timing sample of plain
+    // launches; graphs replay the others
+    bool sample = false;
+    if (h->timing) sample = (h->chunk_seq++ % (uint64_t)h->time_every) == 0;
+    const bool graph_ok = h->use_graph && !sample && chunk_is_full;
     if (!graph_ok) {
+        h->time_now = sample;
         int rc = enqueue_chunk(h, upd, n, k0, false);
+        h->time_now = true;
         if (rc) return rc;
         return count_chunk(h, n);
     }
     int tailkey = 0;
     if (h->storage == GF_MIXED_F32_R12 && h->tail_theta > 0.0)
         tailkey = (h->n_tail == 0) ? 1 : (h->n_tail >= h->n_active ? 2 : 3);
-    GraphCache &g = h->graph;
     const int wkey = (h->W[0] * 16 + h->W[1]) * 16 + h->W[2];
-    if (!(g.exec && g.key_upd == upd && g.key_n == n && g.key_W == wkey && g.key_tail == tailkey)) {
-        g.clear();
+    const int rkey = (R > 0) ? k0 % R : 0;  // which sweeps of the chunk reproject
+    GraphCache &gc = h->graph;
+    GraphEntry *g = nullptr;
+    for (auto &x : gc.e)
+        if (x.key_upd == upd && x.key_n == n && x.key_W == wkey && x.key_tail == tailkey && x.key_r == rkey) g = &x;
+    if (!g) {
+        if (gc.e.size() >= GraphCache::kMax) gc.clear();
         if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
         HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
         h->cur = h->cap;
-        int rc = enqueue_chunk(h, upd, n, 0, true);
+        int rc = enqueue_chunk(h, upd, n, rkey, true);
         if (rc == GF_OK) rc = count_chunk(h, n);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(h->cap, &gr);
@@ -579,14 +597,22 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
             return rc;
         }
         if (e != hipSuccess) return fail(h, GF_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-        g.graph = gr;
-        HIPCHK(h, hipGraphInstantiate(&g.exec, gr, nullptr, nullptr, 0));
-        g.key_upd = upd;
-        g.key_n = n;
-        g.key_W = wkey;
-        g.key_tail = tailkey;
+        GraphEntry ne;
+        ne.graph = gr;
+        hipError_t ie = hipGraphInstantiate(&ne.exec, gr, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(gr);
+            return fail(h, GF_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+        }
+        ne.key_upd = upd;
+        ne.key_n = n;
+        ne.key_W = wkey;
+        ne.key_tail = tailkey;
+        ne.key_r = rkey;
+        gc.e.push_back(ne);
+        g = &gc.e.back();
     }
-    HIPCHK(h, hipGraphLaunch(g.exec, h->stream));
+    HIPCHK(h, hipGraphLaunch(g->exec, h->stream));
     return GF_OK;
 }
 
@@ -1191,7 +1217,7 @@ int gf_set_timing(gf_handle h, int every) {
     if (rc) return rc;
     h->timing = every != 0;
     h->time_every = every > 0 ? every : 1;
-    h->launch_seq = 0;
+    h->chunk_seq = 0;
     h->t_sum_ms[0] = h->t_sum_ms[1] = 0.0;
     h->t_count[0] = h->t_count[1] = 0;
     return GF_OK;
