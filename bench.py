@@ -279,12 +279,15 @@ def golden_F():
 
 
 def main():
+    global TAIL
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison runs")
+    ap.add_argument("--fp64-tail", type=float, default=None,
+                    help="compute the update in FP64 once a unit's theta is below this (default %g)" % TAIL)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (scale for rocprof byte counters)")
     ap.add_argument("--workloads", action="store_true",
@@ -294,6 +297,8 @@ def main():
     ap.add_argument("--profile-sweeps", type=int, default=0,
                     help="only run this many OR sweeps of the workload (for profiler counter runs)")
     args = ap.parse_args()
+    if args.fp64_tail is not None:
+        TAIL = args.fp64_tail
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the gauge-fixing path is not sharded across GPUs); "
               "run with --gpus 1", file=sys.stderr)
