@@ -37,7 +37,8 @@
  *   R8 MAG theta (Sec. 2.1.2) for SU(3): sum over i<j of |Gamma_ij|^2 with
  *      Gamma = W - W^dag, W = sum_mu [U D(U)^dag - D(U')^dag U'], D() the
  *      diagonal part, U' the backward link; the literal squared-sum form is
- *      reported separately;
+ *      reported separately (gfo_theta_mag_literal: parity unpinned, the
+ *      printed form being ambiguous; nothing depends on it);
  *   R9 Coulomb: 3D parity (x+y+z) mod 2 inside each time-slice, F and theta
  *      normalised per time-slice with 3 spatial directions, G(x) accumulates
  *      the transformation, U_0(x) <- G(x) U_0(x) G(x+0)^dag at the end
@@ -847,7 +848,8 @@ double gfo_theta_mag_via_subgroups(const double *U, const int32_t dims[4]) {
     return Ts / (3.0 * (double)g.V);
 }
 
-/* MAG theta in the literal squared-sum form of Sec. 2.1.2 (reported only) */
+/* MAG theta in the literal squared-sum form of Sec. 2.1.2 (reported only;
+   parity unpinned: the printed form is ambiguous and nothing depends on it) */
 double gfo_theta_mag_literal(const double *U, const int32_t dims[4]) {
     geom g = make_geom(dims);
     double Ts = 0.0;
