@@ -150,6 +150,8 @@ def workloads(gf, I):
       overrelaxation omega 1.7 to theta < 1e-12, FP32-12 storage;
     * 64^3 x 256 Coulomb: time per sweep (checks every 20 sweeps included)
       without and with Infinity-Cache groups;
+    * MAG on a hot 16^4 configuration: annealing temperature scan, then
+      overrelaxation;
     * 32 Gribov copies (8 random gauge copies each of 16^4, 24^4, 40x20^3,
       64x32^3, eps 0.5) fixed to Landau gauge in one batched launch,
       theta < 1e-12 per copy, FP32-12 storage."""
@@ -203,6 +205,29 @@ def workloads(gf, I):
                                                  "GBs": round(672 * 256 * vs / (ms * 1e-3) / 1e9)}
     fx.close()
     print(json.dumps(out), flush=True)
+
+    # MAG on a hot (Haar-random) 16^4 configuration: annealing from several
+    # starting temperatures to T = 0.01 (1000 steps, 3 microcanonical sweeps
+    # each), then overrelaxation to theta < 1e-12 (at most 20000 sweeps)
+    dims = (16, 16, 16, 16)
+    hot = torch.from_numpy(I.hot(dims, 6001).reshape(-1)).to("cuda:0")
+    scan = []
+    for T0 in (0.5, 1.0, 1.5, 2.0):
+        fx = gf.GaugeFixer([dims], gauge="mag", storage="mixed", reunit_every=100, tail_theta=1e-9)
+        fx.upload(0, hot)
+        fx.set_overrelax(OMEGA)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fx.set_anneal(T0, 0.01, 1000, nmicro=3, seed=6002)
+        fx.sweep("anneal")
+        F_sa, _ = fx.measure(0)
+        st, done = fx.sweep("or", max_sweeps=20000, tol=TOL, check_every=CHECK)
+        torch.cuda.synchronize()
+        F, th = fx.measure(0)
+        scan.append({"T0": T0, "F_after_anneal": round(F_sa, 9), "or_sweeps": int(done[0]), "status": st,
+                     "F": round(F, 12), "theta": th, "s": round(time.perf_counter() - t0, 3)})
+        fx.close()
+    print(json.dumps({"workload": "mag-16^4-hot-anneal-temperature-scan", "scan": scan}), flush=True)
 
     shapes = [(16, 16, 16, 16), (24, 24, 24, 24), (40, 20, 20, 20), (64, 32, 32, 32)]
     ncopy = 8
