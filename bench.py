@@ -94,7 +94,7 @@ def one_fix(fx, inp):
     """upload (device-resident natural layout) + fix + final FP64 reprojection; returns sweeps"""
     fx.upload(0, inp)
     st, done = fx.sweep("or", max_sweeps=MAX_SWEEPS, tol=TOL, check_every=CHECK)
-    if fx.storage == 2:
+    if fx.storage in (2, 3):  # FP32 storages: final FP64 reprojection
         fx.reunitarise()
     return st, int(done[0])
 
@@ -152,6 +152,7 @@ def workloads(gf, I):
       without and with Infinity-Cache groups;
     * MAG on a hot 16^4 configuration: annealing temperature scan, then
       overrelaxation;
+    * precision study: 32^4 Landau seed 2001 in single, mixed and FP64-12;
     * 32 Gribov copies (8 random gauge copies each of 16^4, 24^4, 40x20^3,
       64x32^3, eps 0.5) fixed to Landau gauge in one batched launch,
       theta < 1e-12 per copy, FP32-12 storage."""
@@ -179,6 +180,33 @@ def workloads(gf, I):
     print(json.dumps({"workload": "mag-32^4-eps0.7-anneal3000-T1.5to0.01-then-or", "anneal_s": round(t_sa, 3),
                       "anneal_sweeps": 12000, "F_after_anneal": F_sa, "or_sweeps": int(done[0]), "status": st,
                       "total_s": round(t_all, 3), "F": F, "theta": th}), flush=True)
+
+    # precision study (Sec. 4.5): the 32^4 Landau fix of seed 2001 in single
+    # precision, mixed precision and FP64, against the oracle's F
+    gold = golden_F().get(SEEDS[0])
+    inp = torch.from_numpy(I.smooth(DIMS, EPS, SEEDS[0]).reshape(-1)).to("cuda:0")
+    study = []
+    for storage, R in (("single", REUNIT), ("mixed", REUNIT), ("f64r12", 0)):
+        fx = gf.GaugeFixer([DIMS], gauge="landau", storage=storage, reunit_every=R, tail_theta=0.0)
+        fx.upload(0, inp)
+        fx.set_overrelax(OMEGA)
+        fx.autotune(reps=3)
+        fx.upload(0, inp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, done = fx.sweep("or", max_sweeps=MAX_SWEEPS, tol=TOL, check_every=CHECK)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        umean, umax = fx.unitarity(0)
+        if storage != "f64r12":
+            fx.reunitarise()
+        F, th = fx.measure(0)
+        fx.close()
+        study.append({"storage": storage, "reunit_every": R, "status": st, "sweeps": int(done[0]),
+                      "s": round(el, 4), "F": F, "theta": th, "unitarity_max_at_stop": umax,
+                      "F_rel_err_vs_oracle": abs(F - gold["F"]) / gold["F"] if gold else None})
+    del inp
+    print(json.dumps({"workload": "landau-32^4-seed2001-precision-study", "runs": study}), flush=True)
 
     # 64^3 x 256 Coulomb sweep throughput: 16 generated time-slices repeated
     # 16 times (the cost of a sweep does not depend on the link values), 40

@@ -62,6 +62,8 @@ typedef struct gf_ctx *gf_handle;
 #define GF_F64_R18 0       /* double, all 18 reals */
 #define GF_F64_R12 1       /* double, first two rows; third row = (u x v)^* */
 #define GF_MIXED_F32_R12 2 /* float, first two rows; G applied, reductions and reprojection in FP64 */
+#define GF_F32_R12 3       /* float, first two rows; all arithmetic of the sweep in FP32, reductions and
+                              reprojection in FP64 (the single precision of Sec. 4.5) */
 
 /* gf_download flags */
 #define GF_DL_REUNITARISE 1 /* reproject every link to SU(3) in FP64 while converting */
@@ -92,13 +94,13 @@ int gf_add_instance(gf_handle h, const int32_t dims[4], int32_t *inst);
    temporal links at the end of each gf_sweep (Sec. 5).  Only before binding. */
 int gf_set_gauge(gf_handle h, int gauge);
 
-/* Storage (GF_F64_R18, GF_F64_R12, GF_MIXED_F32_R12), reprojection interval
+/* Storage (GF_F64_R18, GF_F64_R12, GF_MIXED_F32_R12, GF_F32_R12), reprojection interval
    (inside gf_sweep, reproject the links of every unit still running after
    every `reunit_every` sweeps; 0 = never, Sec. 4.5) and, for mixed storage,
    the threshold below which the local update is computed in FP64 instead of
    FP32 (the "final iterations" of a run): compute in FP64 once the last
    measured theta of a unit is below `fp64_tail_theta` (0 = never, >= 1e300 =
-   always).  Mixed storage always applies the product G of a site's three
+   always; mixed storage only).  Mixed storage always applies the product G of a site's three
    subgroup elements to its links in FP64, after reprojecting a G built in
    FP32 to SU(3), and rounds the result to FP32.  12-real storages store a
    left-multiplied link after one first-order renormalisation of its two rows

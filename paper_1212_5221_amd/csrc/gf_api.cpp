@@ -412,6 +412,7 @@ int drain_timing(gf_ctx *h) {
 int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sweep_off, int grp = -1) {
     const int st = st_code(h->storage);
     const bool mixed = (h->storage == GF_MIXED_F32_R12);
+    const bool single = (h->storage == GF_F32_R12);
     const bool hb = (upd == gfs::UPD_HEATBATH || upd == gfs::UPD_SR);
     // compute precision: FP64 storage -> double; mixed -> float (+ double tail)
     // ctd: compute precision of the update (0 FP32, 1 FP64); tab: tile table
@@ -423,6 +424,8 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
         launches[nl++] = {h->force_ctd, -1, h->force_ctd};
     } else if (upd == gfs::UPD_HEATBATH) {
         launches[nl++] = {1, -1, 2};
+    } else if (single && !hb) {
+        launches[nl++] = {0, -1, 0};
     } else if (!mixed || hb) {
         launches[nl++] = {1, -1, 1};
     } else if (h->tail_theta > 0.0) {
@@ -440,7 +443,9 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
     }
     for (int k = 0; k < nl; ++k) {
         const int ctd = launches[k].ctd, tab = launches[k].tab;
-        gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, st, ctd, h->W[tab]);
+        // single precision: the FP32-update kernels that also apply G in FP32
+        const int kst = (single && ctd == 0) ? (int)gfs::ST_F32R12_SP : st;
+        gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, kst, ctd, h->W[tab]);
         if (!fn) return fail(h, GF_E_INVALID, "no kernel variant for gauge %d update %d storage %d W %d", h->gauge, upd,
                              h->storage, h->W[tab]);
         int nt = 0;
@@ -718,7 +723,7 @@ int gf_set_gauge(gf_handle h, int gauge) {
 int gf_set_precision(gf_handle h, int storage, int32_t reunit_every, double fp64_tail_theta) {
     int rc = check_unbound(h);
     if (rc) return rc;
-    if (storage != GF_F64_R18 && storage != GF_F64_R12 && storage != GF_MIXED_F32_R12)
+    if (storage != GF_F64_R18 && storage != GF_F64_R12 && storage != GF_MIXED_F32_R12 && storage != GF_F32_R12)
         return fail(h, GF_E_INVALID, "bad storage %d", storage);
     if (reunit_every < 0) return fail(h, GF_E_INVALID, "reunit_every < 0");
     if (!(fp64_tail_theta >= 0.0)) return fail(h, GF_E_INVALID, "fp64_tail_theta must be >= 0");
@@ -1106,6 +1111,7 @@ int gf_set_sweep_index(gf_handle h, int32_t inst, uint64_t index) {
 
 // compute precisions of the update this configuration uses (bit 0 FP32, bit 1 FP64)
 static int used_precisions(const gf_ctx *h) {
+    if (h->storage == GF_F32_R12) return 1;
     if (h->storage != GF_MIXED_F32_R12) return 2;
     if (h->tail_theta <= 0.0) return 1;
     if (h->tail_theta >= 1e300) return 2;

@@ -242,6 +242,9 @@ struct Store<gfs::ST_F32R12> {
 };
 
 template <>
+struct Store<gfs::ST_F32R12_SP> : Store<gfs::ST_F32R12> {};
+
+template <>
 struct Store<gfs::ST_F64R12> {
     typedef double S;
     typedef double2 V;

@@ -33,6 +33,10 @@ sweep_fn sweep_kernel_coulomb(int upd, int st, int ctd, int W) {
     if (W == 2 && upd == gfs::UPD_SR && st == gfs::ST_F64R18 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_SR, gfs::ST_F64R18, double, 2>;
     if (W == 2 && upd == gfs::UPD_SR && st == gfs::ST_F64R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_SR, gfs::ST_F64R12, double, 2>;
     if (W == 2 && upd == gfs::UPD_SR && st == gfs::ST_F32R12 && ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_SR, gfs::ST_F32R12, double, 2>;
+    if (W == 1 && upd == gfs::UPD_OR && st == gfs::ST_F32R12_SP && !ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_OR, gfs::ST_F32R12_SP, float, 1>;
+    if (W == 1 && upd == gfs::UPD_MICRO && st == gfs::ST_F32R12_SP && !ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_MICRO, gfs::ST_F32R12_SP, float, 1>;
+    if (W == 2 && upd == gfs::UPD_OR && st == gfs::ST_F32R12_SP && !ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_OR, gfs::ST_F32R12_SP, float, 2>;
+    if (W == 2 && upd == gfs::UPD_MICRO && st == gfs::ST_F32R12_SP && !ctd) return &gfd::k_sweep<gfs::COULOMB, gfs::UPD_MICRO, gfs::ST_F32R12_SP, float, 2>;
     return nullptr;
 }
 

@@ -27,12 +27,13 @@ OK, NOT_CONVERGED = 0, 1
 E_INVALID, E_DIMS, E_STATE, E_HIP, E_NOMEM, E_NONFINITE = -1, -2, -3, -4, -5, -6
 LANDAU, COULOMB, MAG = 0, 1, 2
 OR, MICRO, ANNEAL, SR, HEATBATH = 0, 1, 2, 3, 4
-F64_R18, F64_R12, MIXED_F32_R12 = 0, 1, 2
+F64_R18, F64_R12, MIXED_F32_R12, F32_R12 = 0, 1, 2, 3
 DL_REUNITARISE = 1
 
 GAUGES = {"landau": LANDAU, "coulomb": COULOMB, "mag": MAG}
 UPDATES = {"or": OR, "micro": MICRO, "anneal": ANNEAL, "sr": SR, "heatbath": HEATBATH}
-STORAGES = {"f64r18": F64_R18, "f64r12": F64_R12, "mixed": MIXED_F32_R12, "f32r12": MIXED_F32_R12}
+STORAGES = {"f64r18": F64_R18, "f64r12": F64_R12, "mixed": MIXED_F32_R12, "f32r12": MIXED_F32_R12,
+            "single": F32_R12}
 
 _lib = None
 
