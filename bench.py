@@ -53,8 +53,8 @@ BYTES_PER_SITE = {"mixed": 768, "f64r12": 1536, "f64r18": 2304}  # 8 links loade
 COUNTER_SOURCES = ("paper_1212_5221_amd/csrc/gf_sweep.hpp", "paper_1212_5221_amd/csrc/gf_device.hpp",
                    "paper_1212_5221_amd/csrc/gf_shared.hpp", "paper_1212_5221_amd/csrc/gf_sweep_landau.hip",
                    "paper_1212_5221_amd/build.py")
-COUNTER_DIGEST = "f002a4c8110eeb60"
-COUNTER_TRAFFIC = {1: 402906886, 2: 402935762, 4: 402952145}
+COUNTER_DIGEST = "8310eaf69405bac7"
+COUNTER_TRAFFIC = {1: 402902713, 2: 402935685, 4: 402951454}
 
 
 def kernel_digest():
@@ -296,13 +296,13 @@ def kernel_table(gf, I, nsweeps=20):
     autotuned, nsweeps sweeps with kernel timing; one JSON line each."""
     V = int(np.prod(DIMS))
     U = I.smooth(DIMS, EPS, SEEDS[0])
-    link = {"mixed": 48, "f64r12": 96, "f64r18": 144}
+    link = {"mixed": 48, "single": 48, "f64r12": 96, "f64r18": 144}
     for gauge in ("landau", "coulomb", "mag"):
         nl = 6 if gauge == "coulomb" else 8
-        for storage in ("mixed", "f64r12", "f64r18"):
+        for storage in ("mixed", "single", "f64r12", "f64r18"):
             # algorithmic bytes per site update: links loaded and stored (+ G for Coulomb)
             bps = 2 * nl * link[storage] + (2 * link[storage] if gauge == "coulomb" else 0)
-            for upd in ("or", "heatbath"):
+            for upd in (("or",) if storage == "single" else ("or", "heatbath")):
                 fx = gf.GaugeFixer([DIMS], gauge=gauge, storage=storage, reunit_every=0, tail_theta=0.0)
                 fx.set_cache_budget(0)  # one launch per half-sweep over all time-slices
                 fx.upload(0, U)
