@@ -82,3 +82,44 @@ def test_size_limit_and_bad_arguments():
         fx.set_timing(True, every=-1)
     assert e.value.code == gf.E_INVALID
     fx.close()
+
+
+def test_two_handles_interleaved():
+    # two handles (own workspaces, own graphs) on the same stream, their
+    # sweeps interleaved chunk by chunk, end where each ends alone
+    say("two handles")
+    dims = (4, 4, 6, 4)
+    UA = I.smooth(dims, 0.5, 63)
+    UB = I.smooth(dims, 0.5, 64)
+
+    def alone(U):
+        fx = fixer([dims], "landau", "mixed", reunit_every=5)
+        fx.upload(0, U)
+        fx.set_overrelax(1.7)
+        st, done = fx.sweep("or", max_sweeps=3000, tol=1e-12, check_every=10)
+        out = fx.download(0)
+        fx.close()
+        return st, done, out
+
+    ra, rb = alone(UA), alone(UB)
+    fa = fixer([dims], "landau", "mixed", reunit_every=5)
+    fb = fixer([dims], "landau", "mixed", reunit_every=5)
+    fa.upload(0, UA)
+    fb.upload(0, UB)
+    for f in (fa, fb):
+        f.set_overrelax(1.7)
+    da = db = 0
+    for _ in range(300):
+        if da >= 0:
+            st, d = fa.sweep("or", max_sweeps=10, tol=1e-12, check_every=10)
+            da = -1 if st == 0 else da
+        if db >= 0:
+            st, d = fb.sweep("or", max_sweeps=10, tol=1e-12, check_every=10)
+            db = -1 if st == 0 else db
+        if da < 0 and db < 0:
+            break
+    assert da < 0 and db < 0
+    np.testing.assert_array_equal(fa.download(0), ra[2])
+    np.testing.assert_array_equal(fb.download(0), rb[2])
+    fa.close()
+    fb.close()
