@@ -23,8 +23,11 @@
  *   - Links exchanged with the caller are in the natural order (Sec. 4.2.1,
  *     "StandardPattern"): t, x, y, z, mu, i, j, re/im with z fastest, 18
  *     doubles per link, mu = 0 the time direction.  Boundaries are periodic.
- *   - Common errors: a NULL handle or output pointer, an instance number out
- *     of range or a value outside its documented range gives GF_E_INVALID;
+ *   - Common errors: a NULL handle or a NULL required pointer (the outputs of
+ *     gf_measure, gf_measure_timeslices, gf_unitarity, gf_autotune and
+ *     gf_sweep's sweeps_done may be NULL and are then not written), an
+ *     instance number out of range or a value outside its documented range
+ *     gives GF_E_INVALID;
  *     a call that needs a bound workspace before gf_bind_workspace, or a
  *     configuration call after it, gives GF_E_STATE; a failing HIP call
  *     gives GF_E_HIP with the runtime's message.  Host pointers passed in
