@@ -37,7 +37,7 @@ struct GraphEntry {
 };
 
 struct GraphCache {
-    static constexpr size_t kMax = 8;
+    static constexpr size_t kMax = 16;
     std::vector<GraphEntry> e;
     void clear() {
         for (auto &g : e) {
@@ -582,7 +582,17 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
     if (h->storage == GF_MIXED_F32_R12 && h->tail_theta > 0.0)
         tailkey = (h->n_tail == 0) ? 1 : (h->n_tail >= h->n_active ? 2 : 3);
     const int wkey = (h->W[0] * 16 + h->W[1]) * 16 + h->W[2];
-    const int rkey = (R > 0) ? k0 % R : 0;  // which sweeps of the chunk reproject
+    // which sweeps of the chunk reproject: none or one (R >= n, keyed by the
+    // position), or a pattern fixed by k0 mod R (R < n)
+    int rkey = -1;
+    if (R > 0) {
+        if (R >= n) {
+            const int p = R - 1 - k0 % R;
+            rkey = (p < n) ? p : -1;
+        } else {
+            rkey = n + k0 % R;
+        }
+    }
     GraphCache &gc = h->graph;
     GraphEntry *g = nullptr;
     for (auto &x : gc.e)
@@ -592,7 +602,7 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
         if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
         HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
         h->cur = h->cap;
-        int rc = enqueue_chunk(h, upd, n, rkey, true);
+        int rc = enqueue_chunk(h, upd, n, k0, true);
         if (rc == GF_OK) rc = count_chunk(h, n);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(h->cap, &gr);
