@@ -225,3 +225,36 @@ def test_c4_mag_anneal_full_size():
     assert r.status == 0
     if ddia < 2e-2:
         assert abs(F - Fr) < 2 * f_orbit_tol(done[0], np.prod(dims)) * Fr
+
+
+@pytest.mark.parametrize("storage", ["f64r18", "mixed"])
+def test_checkpoint_files_resume_bit_identically(storage, tmp_path):
+    # annealing in two halves with a checkpoint on disk in between equals the
+    # uninterrupted run (mixed storage: the FP32 links round-trip exactly).
+    # Schedule T 1 -> 0.5 over 5 steps (T_k = 1 - k/8, exact in binary),
+    # split into the steps k = 0..2 and k = 3..4.
+    from paper_1212_5221_amd import checkpoint
+    dims = (4, 4, 4, 4)
+    say("checkpoint files", storage)
+    U = I.smooth(dims, 0.7, 4006)
+    a = fixer([dims, dims], "mag", storage)
+    a.upload(0, U)
+    a.upload(1, U[::-1].copy())
+    a.set_anneal(1.0, 0.5, 5, nmicro=3, seed=11)
+    a.sweep("anneal")
+    full = [a.download(0), a.download(1)]
+    a.close()
+    b = fixer([dims, dims], "mag", storage)
+    b.upload(0, U)
+    b.upload(1, U[::-1].copy())
+    b.set_anneal(1.0, 0.75, 3, nmicro=3, seed=11)
+    b.sweep("anneal")
+    checkpoint.save(b, str(tmp_path), extra={"step": 3})
+    b.close()
+    c = fixer([dims, dims], "mag", storage)
+    assert checkpoint.load(c, str(tmp_path)) == {"step": 3}
+    c.set_anneal(0.625, 0.5, 2, nmicro=3, seed=11)
+    c.sweep("anneal")
+    np.testing.assert_array_equal(c.download(0), full[0])
+    np.testing.assert_array_equal(c.download(1), full[1])
+    c.close()
