@@ -93,6 +93,17 @@ def _load():
     L.gfo_exp_inverse_cdf.restype = _d
     L.gfo_sample_r0.argtypes = [_d, u64p, _u64, _u64, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     L.gfo_sample_r0.restype = _d
+    L.gfo2_halfsweep.argtypes = [_dp, _I32_4, _i32, _i32, _i32, _d, _d, _d, _u64, _u64, _u64, _dp, u8p]
+    L.gfo2_update_sites.argtypes = [_dp, _I32_4, _i32, _i32, _d, _d, _d, _u64, _u64, _u64, _dp, i64p, _i64]
+    L.gfo2_local_g.argtypes = [_dp, _dp, _i32, _i32, _i32, _d, _d, _d, _u64, _u64, _u64, _u64, _dp]
+    L.gfo2_measure.argtypes = [_dp, _I32_4, _i32, _dp, _dp]
+    L.gfo2_measure_slices.argtypes = [_dp, _I32_4, _dp, _dp]
+    L.gfo2_unitarity.argtypes = [_dp, _i64, _dp, _dp]
+    L.gfo2_reunitarise.argtypes = [_dp, _i64]
+    L.gfo2_plaquette.argtypes = [_dp, _I32_4]
+    L.gfo2_plaquette.restype = _d
+    L.gfo2_apply_gauge.argtypes = [_dp, _I32_4, _dp]
+    L.gfo2_coulomb_fix_u0.argtypes = [_dp, _I32_4, _dp]
     _lib = L
     return L
 
@@ -353,3 +364,132 @@ def sample_r0(a, key, sweep, site, subgroup):
     tries = ctypes.c_int()
     r0 = _load().gfo_sample_r0(float(a), k, int(sweep), int(site), int(subgroup), ctypes.byref(tries))
     return r0, tries.value
+
+
+# ---------------------------------------------------------------- SU(2)
+# Links of the SU(2) gauge group: (sites, 4, 2, 2, 2) float64, 8 reals per
+# link; gauge fields (Coulomb G): (sites, 2, 2, 2).
+def _check_links2(U, dims):
+    assert U.dtype == np.float64 and U.flags.c_contiguous, "links must be contiguous float64"
+    assert U.size == _nsites(dims) * 32, "SU(2) links must hold V*4*8 reals"
+
+
+def su2_identity_field(V: int) -> np.ndarray:
+    g = np.zeros((V, 2, 2, 2))
+    g[:, 0, 0, 0] = g[:, 1, 1, 0] = 1.0
+    return g
+
+
+def su2_halfsweep(U, dims, gauge, update, parity, omega=1.0, T=0.0, p_sr=0.5, seed=0, instance=0, sweep=0,
+                  G=None, slice_active=None):
+    _check_links2(U, dims)
+    sa = None
+    if slice_active is not None:
+        slice_active = np.ascontiguousarray(slice_active, dtype=np.uint8)
+        sa = slice_active.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    _load().gfo2_halfsweep(_ptr(U), _dims(dims), _gauge(gauge), _update(update), int(parity), float(omega),
+                           float(T), float(p_sr), int(seed), int(instance), int(sweep),
+                           _ptr(G) if G is not None else None, sa)
+
+
+def su2_sweep(U, dims, gauge, update, omega=1.0, T=0.0, p_sr=0.5, seed=0, instance=0, sweep=0, G=None,
+              slice_active=None):
+    for p in (0, 1):
+        su2_halfsweep(U, dims, gauge, update, p, omega, T, p_sr, seed, instance, sweep, G, slice_active)
+
+
+def su2_update_sites(U, dims, gauge, update, sites, omega=1.0, T=0.0, p_sr=0.5, seed=0, instance=0, sweep=0,
+                     G=None):
+    _check_links2(U, dims)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    _load().gfo2_update_sites(_ptr(U), _dims(dims), _gauge(gauge), _update(update), float(omega), float(T),
+                              float(p_sr), int(seed), int(instance), int(sweep),
+                              _ptr(G) if G is not None else None,
+                              sites.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(sites))
+
+
+def su2_local_g(fwd, bwd, gauge, update, omega=1.0, T=0.0, p_sr=0.5, seed=0, instance=0, sweep=0, site=0):
+    """g(x) (2x2 complex as 8 reals) from ndir forward and backward links."""
+    fwd = np.ascontiguousarray(fwd, dtype=np.float64)
+    bwd = np.ascontiguousarray(bwd, dtype=np.float64)
+    out = np.empty(8)
+    _load().gfo2_local_g(_ptr(fwd), _ptr(bwd), fwd.size // 8, _gauge(gauge), _update(update), float(omega),
+                         float(T), float(p_sr), int(seed), int(instance), int(sweep), int(site), _ptr(out))
+    return out.reshape(2, 2, 2)
+
+
+def su2_measure(U, dims, gauge):
+    _check_links2(U, dims)
+    F = ctypes.c_double()
+    th = ctypes.c_double()
+    _load().gfo2_measure(_ptr(U), _dims(dims), _gauge(gauge), ctypes.byref(F), ctypes.byref(th))
+    return F.value, th.value
+
+
+def su2_measure_slices(U, dims):
+    _check_links2(U, dims)
+    Nt = int(dims[0])
+    F = np.empty(Nt)
+    th = np.empty(Nt)
+    _load().gfo2_measure_slices(_ptr(U), _dims(dims), _ptr(F), _ptr(th))
+    return F, th
+
+
+def su2_unitarity(U):
+    U = np.ascontiguousarray(U)
+    m = ctypes.c_double()
+    x = ctypes.c_double()
+    _load().gfo2_unitarity(_ptr(U), U.size // 8, ctypes.byref(m), ctypes.byref(x))
+    return m.value, x.value
+
+
+def su2_reunitarise(U):
+    assert U.dtype == np.float64 and U.flags.c_contiguous
+    _load().gfo2_reunitarise(_ptr(U), U.size // 8)
+
+
+def su2_plaquette(U, dims):
+    _check_links2(U, dims)
+    return _load().gfo2_plaquette(_ptr(U), _dims(dims))
+
+
+def su2_apply_gauge(U, dims, g):
+    _check_links2(U, dims)
+    _load().gfo2_apply_gauge(_ptr(U), _dims(dims), _ptr(np.ascontiguousarray(g, dtype=np.float64)))
+
+
+def su2_coulomb_fix_u0(U, dims, G):
+    _check_links2(U, dims)
+    _load().gfo2_coulomb_fix_u0(_ptr(U), _dims(dims), _ptr(np.ascontiguousarray(G)))
+
+
+def su2_run(U, dims, gauge, update="or", omega=1.7, max_sweeps=1000, tol=1e-12, check_every=1):
+    """Sweeps until theta < tol at a check (Landau, MAG; Coulomb: every
+    time-slice stops on its own and U_0 is fixed up at the end).  Returns
+    (status, sweeps per unit)."""
+    _check_links2(U, dims)
+    if _gauge(gauge) != COULOMB:
+        k = 0
+        while True:
+            if k % check_every == 0 and su2_measure(U, dims, gauge)[1] < tol:
+                return 0, [k]
+            if k >= max_sweeps:
+                return 1, [k]
+            su2_sweep(U, dims, gauge, update, omega=omega, sweep=k)
+            k += 1
+    Nt = int(dims[0])
+    G = np.ascontiguousarray(np.broadcast_to(su2_identity_field(1), (_nsites(dims), 2, 2, 2)))
+    active = np.ones(Nt, np.uint8)
+    done = np.zeros(Nt, np.int64)
+    k = 0
+    while True:
+        if k % check_every == 0:
+            th = su2_measure_slices(U, dims)[1]
+            active &= (th >= tol).astype(np.uint8)
+        if not active.any() or k >= max_sweeps:
+            break
+        su2_sweep(U, dims, COULOMB, update, omega=omega, sweep=k, G=G, slice_active=active)
+        done += active
+        k += 1
+    su2_coulomb_fix_u0(U, dims, G)
+    return (0 if not active.any() else 1), list(done)

@@ -1,5 +1,5 @@
 /*
- * gf_oracle.c -- plain FP64 CPU oracle for SU(3) lattice gauge fixing
+ * gf_oracle.c -- plain FP64 CPU oracle for SU(3) and SU(2) lattice gauge fixing
  * (Schroeck & Vogt, "Coulomb, Landau and Maximally Abelian Gauge Fixing in
  * Lattice QCD with Multi-GPUs", arXiv:1212.5221).
  *
@@ -49,7 +49,12 @@
  *      from Philox4x64-10 keyed (seed, instance), counter (sweep, site,
  *      subgroup<<16 | block, stream);
  *   R11 annealing schedule linear in T, one heatbath sweep then nmicro
- *      microcanonical sweeps per step.
+ *      microcanonical sweeps per step;
+ *   R12 SU(2) gauge group (functions gfo2_*): the MAG term of the backward
+ *      link U_mu(x - mu), which transforms as U_mu(x - mu) g(x)^dag, is the
+ *      forward term of U_mu(x - mu)^dag (the printed local functional leaves
+ *      the second term to the reader); the heatbath weight is
+ *      exp(Re tr[g K] / T) as for an SU(3) subgroup.
  */
 #include <complex.h>
 #include <math.h>
@@ -1113,4 +1118,378 @@ void gfo_anneal(double *U, const int32_t dims[4], int32_t gauge, double T0, doub
             ++*sweep_counter;
         }
     }
+}
+
+/* ================================================================== */
+/* SU(2) gauge group (N_c = 2): Sec. 2.1 and 2.2 for SU(2) itself       */
+/* ================================================================== */
+/*
+ * Links are 2x2 complex matrices in the natural layout
+ * (sites, 4, 2, 2, re/im), 8 reals per link.  The local update is done on
+ * the whole group, with no subgroup iteration:
+ *   Landau/Coulomb: K(x) = sum_mu U_mu(x) + U_mu(x - mu)^dag and the optimum
+ *     g = K^dag / sqrt(det K^dag) (eq. localsolution, written out as matrices);
+ *   MAG: the coefficients D, E, F of the quadratic form of eq. upMatrix in
+ *     the Cayley-Klein components of the links (reading R4: D twice the
+ *     printed value, written without using det U = 1).  The backward link
+ *     transforms as U_mu(x - mu) g(x)^dag, so its term is the forward term
+ *     of U_mu(x - mu)^dag (reading R12);
+ *   overrelaxation, microcanonical and stochastic relaxation steps and both
+ *     heatbaths as for one SU(3) subgroup (readings R5, R6, R10), with the
+ *     random counter's subgroup field 0;
+ *   F and theta as in Sec. 2.1 with N_c = 2: the MAG theta from the
+ *     off-diagonal element of X(x) of Sec. 2.1.2, computed as matrices.
+ */
+
+typedef struct { cplx e[2][2]; } mat2;
+
+static mat2 m2_get(const double *p) {
+    mat2 m;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) m.e[i][j] = CMPLX(p[2 * (2 * i + j)], p[2 * (2 * i + j) + 1]);
+    return m;
+}
+
+static void m2_put(double *p, const mat2 *m) {
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            p[2 * (2 * i + j)] = creal(m->e[i][j]);
+            p[2 * (2 * i + j) + 1] = cimag(m->e[i][j]);
+        }
+}
+
+static mat2 l2_get(const double *U, int64_t s, int mu) { return m2_get(U + ((size_t)s * 4 + mu) * 8); }
+static void l2_put(double *U, int64_t s, int mu, const mat2 *m) { m2_put(U + ((size_t)s * 4 + mu) * 8, m); }
+
+static mat2 m2_zero(void) {
+    mat2 m;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) m.e[i][j] = 0.0;
+    return m;
+}
+
+static mat2 m2_mul(const mat2 *a, const mat2 *b) {
+    mat2 c;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) c.e[i][j] = a->e[i][0] * b->e[0][j] + a->e[i][1] * b->e[1][j];
+    return c;
+}
+
+static mat2 m2_dag(const mat2 *a) {
+    mat2 c;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) c.e[i][j] = conj(a->e[j][i]);
+    return c;
+}
+
+static cplx m2_det(const mat2 *a) { return a->e[0][0] * a->e[1][1] - a->e[0][1] * a->e[1][0]; }
+
+/* Cayley-Klein components of an SU(2) matrix (from its first row) */
+static quat m2_quat(const mat2 *m) {
+    quat q;
+    q.v[0] = creal(m->e[0][0]);
+    q.v[3] = cimag(m->e[0][0]);
+    q.v[2] = creal(m->e[0][1]);
+    q.v[1] = cimag(m->e[0][1]);
+    return q;
+}
+
+static mat2 quat_m2(quat g) {
+    mat2 m;
+    quat_to_2x2(g, m.e);
+    return m;
+}
+
+/* traceless part of (M - M^dag)/(2i) (reading R7 for N_c = 2) */
+static mat2 m2_antiherm_traceless(const mat2 *m) {
+    mat2 a;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) a.e[i][j] = (m->e[i][j] - conj(m->e[j][i])) / (2.0 * I);
+    cplx tr = (a.e[0][0] + a.e[1][1]) / 2.0;
+    a.e[0][0] -= tr;
+    a.e[1][1] -= tr;
+    return a;
+}
+
+static double m2_norm2(const mat2 *a) {
+    double s = 0.0;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) s += creal(a->e[i][j] * conj(a->e[i][j]));
+    return s;
+}
+
+/* the printed MAG coefficients of one link (D doubled, reading R4) */
+static void su2_mag_add(quat u, mag_coef *c) {
+    c->D += u.v[0] * u.v[0] + u.v[3] * u.v[3] - u.v[1] * u.v[1] - u.v[2] * u.v[2];
+    c->E += 2.0 * (-u.v[0] * u.v[1] - u.v[2] * u.v[3]);
+    c->F += 2.0 * (-u.v[0] * u.v[2] + u.v[1] * u.v[3]);
+}
+
+/* Step 1 for SU(2): the g(x) of the update, from the adjacent links */
+static mat2 su2_local(const mat2 *fwd, const mat2 *bwd, int ndir, const upd_params *P, const rng_site *r) {
+    quat gq;
+    if (P->gauge == GFO_MAG) {
+        mag_coef c = {0, 0, 0};
+        for (int k = 0; k < ndir; ++k) su2_mag_add(m2_quat(&fwd[k]), &c);
+        for (int k = 0; k < ndir; ++k) {
+            mat2 bd = m2_dag(&bwd[k]);
+            su2_mag_add(m2_quat(&bd), &c);
+        }
+        if (P->update == GFO_HEATBATH)
+            gq = mag_heatbath(c, P->T, r);
+        else
+            gq = finish_update(mag_relax(c), P, r);
+        return quat_m2(gq);
+    }
+    mat2 K = m2_zero();
+    for (int k = 0; k < ndir; ++k) {
+        mat2 bd = m2_dag(&bwd[k]);
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) K.e[i][j] += fwd[k].e[i][j] + bd.e[i][j];
+    }
+    mat2 Kd = m2_dag(&K);
+    cplx det = m2_det(&Kd);
+    mat2 h;
+    if (det == 0.0) {
+        h = quat_m2(quat_unit());
+    } else {
+        cplx sq = csqrt(det);
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) h.e[i][j] = Kd.e[i][j] / sq;
+    }
+    quat hq = m2_quat(&h);
+    if (P->update == GFO_HEATBATH) {
+        /* g = r h, r0 ~ sqrt(1 - r0^2) exp(a r0) with a T = Re tr[h K], the
+           local functional at the optimum (reading R10) */
+        mat2 hK = m2_mul(&h, &K);
+        double a = creal(hK.e[0][0] + hK.e[1][1]) / P->T;
+        double r0 = gfo_sample_r0(a, r->key, r->sweep, r->site, r->subgroup, NULL);
+        double u[4];
+        draw4(r, 0, 1, u);
+        double ct = 2.0 * u[0] - 1.0;
+        double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+        double phi = 2.0 * M_PI * u[1];
+        double rr = sqrt(fmax(0.0, 1.0 - r0 * r0));
+        quat rq = {{r0, rr * st * cos(phi), rr * st * sin(phi), rr * ct}};
+        mat2 rm = quat_m2(rq);
+        return m2_mul(&rm, &h);
+    }
+    if (P->update == GFO_MICRO) return m2_mul(&h, &h);
+    if (P->update == GFO_SR) {
+        double u[4];
+        draw4(r, 0, 2, u);
+        if (u[0] < P->p_sr) return m2_mul(&h, &h);
+        return h;
+    }
+    return quat_m2(or_map(hq, P->omega));
+}
+
+/* one SU(2) site update: Step 1, then Step 2 on the adjacent links */
+static void su2_update_site(double *U, double *G, const geom *g, int64_t s, const upd_params *P) {
+    const int coulomb = (P->gauge == GFO_COULOMB);
+    const int mu0 = coulomb ? 1 : 0;
+    const int ndir = 4 - mu0;
+    int64_t back[4];
+    mat2 fwd[4], bwd[4];
+    for (int k = 0; k < ndir; ++k) {
+        back[k] = site_shift(g, s, mu0 + k, -1);
+        fwd[k] = l2_get(U, s, mu0 + k);
+        bwd[k] = l2_get(U, back[k], mu0 + k);
+    }
+    rng_site r = {{P->key[0], P->key[1]}, P->sweep, (uint64_t)s, 0};
+    mat2 gx = su2_local(fwd, bwd, ndir, P, &r);
+    mat2 gd = m2_dag(&gx);
+    for (int k = 0; k < ndir; ++k) {
+        mat2 f = m2_mul(&gx, &fwd[k]);
+        mat2 b = m2_mul(&bwd[k], &gd);
+        l2_put(U, s, mu0 + k, &f);
+        l2_put(U, back[k], mu0 + k, &b);
+    }
+    if (coulomb && G) {
+        mat2 Gx = m2_get(G + (size_t)s * 8);
+        mat2 n = m2_mul(&gx, &Gx);
+        m2_put(G + (size_t)s * 8, &n);
+    }
+}
+
+void gfo2_halfsweep(double *U, const int32_t dims[4], int32_t gauge, int32_t update, int32_t parity, double omega,
+                    double T, double p_sr, uint64_t seed, uint64_t instance, uint64_t sweep, double *G,
+                    const uint8_t *slice_active) {
+    geom g = make_geom(dims);
+    upd_params P = {gauge, update, omega, T, p_sr, {seed, instance}, sweep};
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < g.V; ++s)
+        if (site_active(&g, s, gauge, parity, slice_active)) su2_update_site(U, G, &g, s, &P);
+}
+
+void gfo2_update_sites(double *U, const int32_t dims[4], int32_t gauge, int32_t update, double omega, double T,
+                       double p_sr, uint64_t seed, uint64_t instance, uint64_t sweep, double *G,
+                       const int64_t *sites, int64_t nsites) {
+    geom g = make_geom(dims);
+    upd_params P = {gauge, update, omega, T, p_sr, {seed, instance}, sweep};
+    for (int64_t k = 0; k < nsites; ++k) su2_update_site(U, G, &g, sites[k], &P);
+}
+
+/* Step 1 alone on explicit links (unit tests): fwd/bwd are ndir links of 8
+   reals; out receives g(x) as 8 reals */
+void gfo2_local_g(const double *fwd8, const double *bwd8, int32_t ndir, int32_t gauge, int32_t update, double omega,
+                  double T, double p_sr, uint64_t seed, uint64_t instance, uint64_t sweep, uint64_t site,
+                  double out[8]) {
+    mat2 fwd[4], bwd[4];
+    for (int k = 0; k < ndir; ++k) {
+        fwd[k] = m2_get(fwd8 + 8 * k);
+        bwd[k] = m2_get(bwd8 + 8 * k);
+    }
+    upd_params P = {gauge, update, omega, T, p_sr, {seed, instance}, sweep};
+    rng_site r = {{seed, instance}, sweep, site, 0};
+    mat2 gx = su2_local(fwd, bwd, ndir, &P, &r);
+    m2_put(out, &gx);
+}
+
+/* per-site F and theta contributions (Sec. 2.1, N_c = 2) */
+static void su2_site_measure(const double *U, const geom *g, int64_t s, int gauge, double *F, double *T) {
+    const int mu0 = (gauge == GFO_COULOMB) ? 1 : 0;
+    if (gauge == GFO_MAG) {
+        /* X(x) = sum_mu U sigma3 U^dag + U'^dag sigma3 U' (Sec. 2.1.2) */
+        mat2 s3 = m2_zero();
+        s3.e[0][0] = 1.0;
+        s3.e[1][1] = -1.0;
+        mat2 X = m2_zero();
+        for (int mu = 0; mu < 4; ++mu) {
+            mat2 u = l2_get(U, s, mu);
+            for (int i = 0; i < 2; ++i) *F += creal(u.e[i][i] * conj(u.e[i][i]));
+            mat2 ub = l2_get(U, site_shift(g, s, mu, -1), mu);
+            mat2 ud = m2_dag(&u), ubd = m2_dag(&ub);
+            mat2 t1 = m2_mul(&u, &s3), a = m2_mul(&t1, &ud);
+            mat2 t2 = m2_mul(&ubd, &s3), b = m2_mul(&t2, &ub);
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) X.e[i][j] += a.e[i][j] + b.e[i][j];
+        }
+        *T += creal(X.e[0][1] * conj(X.e[0][1]));
+        return;
+    }
+    mat2 Delta = m2_zero();
+    for (int mu = mu0; mu < 4; ++mu) {
+        mat2 u = l2_get(U, s, mu);
+        *F += creal(u.e[0][0] + u.e[1][1]);
+        mat2 ub = l2_get(U, site_shift(g, s, mu, -1), mu);
+        mat2 A = m2_antiherm_traceless(&u), Ab = m2_antiherm_traceless(&ub);
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) Delta.e[i][j] += A.e[i][j] - Ab.e[i][j];
+    }
+    *T += m2_norm2(&Delta);
+}
+
+/* F = (1/(N_c N_d V)) sum (Re tr U | sum_i |U_ii|^2), theta = (1/(N_c V)) sum ... */
+void gfo2_measure(const double *U, const int32_t dims[4], int32_t gauge, double *F_out, double *theta_out) {
+    geom g = make_geom(dims);
+    const int ndir = (gauge == GFO_COULOMB) ? 3 : 4;
+    double Fs = 0.0, Ts = 0.0;
+#pragma omp parallel for reduction(+ : Fs, Ts) schedule(static)
+    for (int64_t s = 0; s < g.V; ++s) {
+        double f = 0.0, t = 0.0;
+        su2_site_measure(U, &g, s, gauge, &f, &t);
+        Fs += f;
+        Ts += t;
+    }
+    *F_out = Fs / (2.0 * ndir * (double)g.V);
+    *theta_out = Ts / (2.0 * (double)g.V);
+}
+
+/* Coulomb: per time-slice F_t and theta_t */
+void gfo2_measure_slices(const double *U, const int32_t dims[4], double *F_t, double *theta_t) {
+    geom g = make_geom(dims);
+    const int64_t Nt = g.n[0], Vs = g.V / Nt;
+    for (int64_t t = 0; t < Nt; ++t) {
+        double Fs = 0.0, Ts = 0.0;
+#pragma omp parallel for reduction(+ : Fs, Ts) schedule(static)
+        for (int64_t k = 0; k < Vs; ++k) {
+            double f = 0.0, th = 0.0;
+            su2_site_measure(U, &g, t * Vs + k, GFO_COULOMB, &f, &th);
+            Fs += f;
+            Ts += th;
+        }
+        F_t[t] = Fs / (6.0 * (double)Vs);
+        theta_t[t] = Ts / (2.0 * (double)Vs);
+    }
+}
+
+/* mean and max |1 - det U| over nlinks links */
+void gfo2_unitarity(const double *U, int64_t nlinks, double *mean, double *maxv) {
+    double s = 0.0, m = 0.0;
+    for (int64_t k = 0; k < nlinks; ++k) {
+        mat2 u = m2_get(U + 8 * (size_t)k);
+        double e = cabs(1.0 - m2_det(&u));
+        s += e;
+        if (e > m) m = e;
+    }
+    *mean = nlinks ? s / (double)nlinks : 0.0;
+    *maxv = m;
+}
+
+/* reprojection to SU(2): normalise row 0, row 1 = (-conj(b), conj(a)) */
+void gfo2_reunitarise(double *U, int64_t nlinks) {
+    for (int64_t k = 0; k < nlinks; ++k) {
+        mat2 u = m2_get(U + 8 * (size_t)k);
+        double n = sqrt(creal(u.e[0][0] * conj(u.e[0][0]) + u.e[0][1] * conj(u.e[0][1])));
+        u.e[0][0] /= n;
+        u.e[0][1] /= n;
+        u.e[1][0] = -conj(u.e[0][1]);
+        u.e[1][1] = conj(u.e[0][0]);
+        m2_put(U + 8 * (size_t)k, &u);
+    }
+}
+
+/* average of (1/2) Re tr of the 1x1 plaquettes over all sites and planes */
+double gfo2_plaquette(const double *U, const int32_t dims[4]) {
+    geom g = make_geom(dims);
+    double s = 0.0;
+#pragma omp parallel for reduction(+ : s) schedule(static)
+    for (int64_t x = 0; x < g.V; ++x)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                mat2 a = l2_get(U, x, mu), b = l2_get(U, site_shift(&g, x, mu, +1), nu);
+                mat2 c = l2_get(U, site_shift(&g, x, nu, +1), mu), d = l2_get(U, x, nu);
+                mat2 cd = m2_dag(&c), dd = m2_dag(&d);
+                mat2 ab = m2_mul(&a, &b), abc = m2_mul(&ab, &cd), p = m2_mul(&abc, &dd);
+                s += 0.5 * creal(p.e[0][0] + p.e[1][1]);
+            }
+    return s / (6.0 * (double)g.V);
+}
+
+/* U_mu(x) <- g(x) U_mu(x) g(x + mu)^dag for a site field g (V x 8 reals) */
+void gfo2_apply_gauge(double *U, const int32_t dims[4], const double *gfield) {
+    geom g = make_geom(dims);
+    double *out = (double *)malloc(sizeof(double) * 32 * (size_t)g.V);
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < g.V; ++s) {
+        mat2 gx = m2_get(gfield + (size_t)s * 8);
+        for (int mu = 0; mu < 4; ++mu) {
+            mat2 gy = m2_get(gfield + (size_t)site_shift(&g, s, mu, +1) * 8);
+            mat2 gyd = m2_dag(&gy), u = l2_get(U, s, mu);
+            mat2 t = m2_mul(&gx, &u), r = m2_mul(&t, &gyd);
+            m2_put(out + ((size_t)s * 4 + mu) * 8, &r);
+        }
+    }
+    memcpy(U, out, sizeof(double) * 32 * (size_t)g.V);
+    free(out);
+}
+
+/* Coulomb finish for SU(2) (reading R9): U_0(x) <- G(x) U_0(x) G(x+0)^dag */
+void gfo2_coulomb_fix_u0(double *U, const int32_t dims[4], const double *G) {
+    geom g = make_geom(dims);
+    double *u0 = (double *)malloc(sizeof(double) * 8 * (size_t)g.V);
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < g.V; ++s) {
+        mat2 gx = m2_get(G + (size_t)s * 8);
+        mat2 gy = m2_get(G + (size_t)site_shift(&g, s, 0, +1) * 8);
+        mat2 gyd = m2_dag(&gy), u = l2_get(U, s, 0);
+        mat2 t = m2_mul(&gx, &u), r = m2_mul(&t, &gyd);
+        m2_put(u0 + (size_t)s * 8, &r);
+    }
+    for (int64_t s = 0; s < g.V; ++s) {
+        mat2 r = m2_get(u0 + (size_t)s * 8);
+        l2_put(U, s, 0, &r);
+    }
+    free(u0);
 }

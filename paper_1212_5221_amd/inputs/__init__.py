@@ -144,3 +144,74 @@ def philox4x64_10(ctr, key) -> np.ndarray:
 def to_complex(U: np.ndarray) -> np.ndarray:
     """View (..., 3, 3, 2) float64 as (..., 3, 3) complex128."""
     return U[..., 0] + 1j * U[..., 1]
+
+
+# ---------------------------------------------------------------- SU(2)
+# SU(2) gauge fields for the SU(2) gauge group: links (V, 4, 2, 2, 2)
+# float64 in the natural order, each the Cayley-Klein matrix
+# [[u0 + i u3, u2 + i u1], [-u2 + i u1, u0 - i u3]] with |u| = 1.  numpy's
+# generator keyed by the seed; the recipes mirror the SU(3) ones:
+#   su2_hot: Haar-random links (normalised Gaussian 4-vectors);
+#   su2_smooth: h(x) exp(i eps xi.sigma) h(x+mu)^dag with xi ~ N(0, 1)^3;
+#   su2_pure_gauge: h(x) h(x+mu)^dag.
+def _su2_matrices(q: np.ndarray) -> np.ndarray:
+    """(..., 4) unit 4-vectors -> (..., 2, 2) complex Cayley-Klein matrices."""
+    m = np.empty(q.shape[:-1] + (2, 2), dtype=np.complex128)
+    m[..., 0, 0] = q[..., 0] + 1j * q[..., 3]
+    m[..., 0, 1] = q[..., 2] + 1j * q[..., 1]
+    m[..., 1, 0] = -q[..., 2] + 1j * q[..., 1]
+    m[..., 1, 1] = q[..., 0] - 1j * q[..., 3]
+    return m
+
+
+def _su2_real(m: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(np.stack([m.real, m.imag], axis=-1))
+
+
+def _su2_haar(rng, shape) -> np.ndarray:
+    q = rng.standard_normal(shape + (4,))
+    q /= np.linalg.norm(q, axis=-1, keepdims=True)
+    return _su2_matrices(q)
+
+
+def su2_gauge_field(dims, seed: int) -> np.ndarray:
+    """A Haar-random gauge transformation h(x), shape (V, 2, 2, 2)."""
+    rng = np.random.default_rng([int(seed), 2, 1])
+    return _su2_real(_su2_haar(rng, (int(np.prod(dims)),)))
+
+
+def su2_hot(dims, seed: int) -> np.ndarray:
+    rng = np.random.default_rng([int(seed), 2, 0])
+    return _su2_real(_su2_haar(rng, (int(np.prod(dims)), 4)))
+
+
+def su2_smooth(dims, eps: float, seed: int) -> np.ndarray:
+    d = tuple(int(x) for x in dims)
+    h = to_complex(su2_gauge_field(d, seed)).reshape(d + (2, 2))
+    rng = np.random.default_rng([int(seed), 2, 2])
+    xi = rng.standard_normal(d + (4, 3))
+    n = np.linalg.norm(xi, axis=-1, keepdims=True)
+    a = float(eps) * n
+    q = np.concatenate([np.cos(a), np.sin(a) * xi / np.where(n > 0, n, 1.0)], axis=-1)
+    w = _su2_matrices(q)
+    out = np.empty(d + (4, 2, 2), dtype=np.complex128)
+    for mu in range(4):
+        hf = np.roll(h, -1, axis=mu)
+        out[..., mu, :, :] = h @ w[..., mu, :, :] @ np.conj(np.swapaxes(hf, -1, -2))
+    return _su2_real(out.reshape((-1, 4, 2, 2)))
+
+
+def su2_pure_gauge(dims, seed: int) -> np.ndarray:
+    return su2_smooth(dims, 0.0, seed)
+
+
+def su2_gauge_copy(U: np.ndarray, dims, seed: int) -> np.ndarray:
+    """A random gauge transform of an SU(2) field (a new array)."""
+    d = tuple(int(x) for x in dims)
+    h = to_complex(su2_gauge_field(d, seed + 7919)).reshape(d + (2, 2))
+    u = to_complex(U).reshape(d + (4, 2, 2))
+    out = np.empty_like(u)
+    for mu in range(4):
+        hf = np.roll(h, -1, axis=mu)
+        out[..., mu, :, :] = h @ u[..., mu, :, :] @ np.conj(np.swapaxes(hf, -1, -2))
+    return _su2_real(out.reshape((-1, 4, 2, 2)))
