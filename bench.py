@@ -293,7 +293,8 @@ def workloads(gf, I):
 def kernel_table(gf, I, nsweeps=20):
     """Half-sweep launch time and effective bandwidth of every gauge x
     storage x update on a 32^4 lattice (Coulomb: 32 time-slices of 32^3),
-    autotuned, nsweeps sweeps with kernel timing; one JSON line each."""
+    autotuned, nsweeps sweeps with kernel timing; one JSON line each; then
+    the same for the gauge group SU(2) (one wavefront per site group)."""
     V = int(np.prod(DIMS))
     U = I.smooth(DIMS, EPS, SEEDS[0])
     link = {"mixed": 48, "single": 48, "f64r12": 96, "f64r18": 144}
@@ -317,7 +318,31 @@ def kernel_table(gf, I, nsweeps=20):
                 fx.set_timing(False)
                 fx.close()
                 gbs = bps * V / 2 / (ms * 1e-3) / 1e9
-                print(json.dumps({"gauge": gauge, "storage": storage, "update": upd, "waves_or": w,
+                print(json.dumps({"group": "su3", "gauge": gauge, "storage": storage, "update": upd,
+                                  "waves_or": w, "launches": n, "mean_launch_ms": round(ms, 5),
+                                  "bytes_per_site_update": bps, "GBs": round(gbs, 1),
+                                  "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}), flush=True)
+    # gauge group SU(2): 4 reals per link (16 bytes FP32, 32 bytes FP64)
+    U2 = I.su2_smooth(DIMS, EPS, SEEDS[0])
+    link2 = {"mixed": 16, "f64r18": 32}
+    for gauge in ("landau", "coulomb", "mag"):
+        nl = 6 if gauge == "coulomb" else 8
+        for storage in ("mixed", "f64r18"):
+            bps = 2 * nl * link2[storage] + (2 * link2[storage] if gauge == "coulomb" else 0)
+            for upd in ("or", "heatbath"):
+                fx = gf.GaugeFixer([DIMS], gauge=gauge, storage=storage, reunit_every=0, tail_theta=0.0, group=2)
+                fx.set_cache_budget(0)
+                fx.upload(0, U2)
+                fx.set_overrelax(OMEGA)
+                fx.set_temperature(0.5)
+                fx.set_seed(7)
+                fx.set_timing(True)
+                fx.sweep(upd, max_sweeps=nsweeps, tol=0.0, check_every=nsweeps)
+                n, ms = fx.kernel_time("all")
+                fx.set_timing(False)
+                fx.close()
+                gbs = bps * V / 2 / (ms * 1e-3) / 1e9
+                print(json.dumps({"group": "su2", "gauge": gauge, "storage": storage, "update": upd,
                                   "launches": n, "mean_launch_ms": round(ms, 5),
                                   "bytes_per_site_update": bps, "GBs": round(gbs, 1),
                                   "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}), flush=True)

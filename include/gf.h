@@ -22,7 +22,8 @@
  *     workspace (gf_workspace_size / gf_bind_workspace) and owns it.
  *   - Links exchanged with the caller are in the natural order (Sec. 4.2.1,
  *     "StandardPattern"): t, x, y, z, mu, i, j, re/im with z fastest, 18
- *     doubles per link, mu = 0 the time direction.  Boundaries are periodic.
+ *     doubles per link (gauge group SU(2): 8), mu = 0 the time direction.
+ *     Boundaries are periodic.
  *   - Common errors: a NULL handle or a NULL required pointer (the outputs of
  *     gf_measure, gf_measure_timeslices, gf_unitarity, gf_autotune and
  *     gf_sweep's sweeps_done may be NULL and are then not written), an
@@ -75,7 +76,7 @@ typedef struct gf_ctx *gf_handle;
                               reprojection in FP64 (the single precision of Sec. 4.5) */
 
 /* gf_download flags */
-#define GF_DL_REUNITARISE 1 /* reproject every link to SU(3) in FP64 while converting */
+#define GF_DL_REUNITARISE 1 /* reproject every link to SU(3) (SU(2)) in FP64 while converting */
 
 /* Create a handle on HIP device `hip_device`.  `hip_stream` is a hipStream_t
    of that device (for example torch.cuda.current_stream().cuda_stream);
@@ -103,6 +104,20 @@ int gf_add_instance(gf_handle h, const int32_t dims[4], int32_t *inst);
    temporal links at the end of each gf_sweep (Sec. 5).  Only before binding. */
 int gf_set_gauge(gf_handle h, int gauge);
 
+/* Gauge group SU(nc), nc = 3 (default) or 2 (else GF_E_INVALID).  For SU(2)
+   the local update acts on the whole group (Sec. 2.2.1 eq. localsolution,
+   Sec. 2.2.2 eq. upMatrix) instead of iterating over subgroups, links are
+   exchanged as 2x2 complex matrices (8 doubles, natural order) and stored
+   as their 4 Cayley-Klein components [[u0 + i u3, u2 + i u1],
+   [-u2 + i u1, u0 - i u3]], read from the first row on upload; F and theta
+   are normalised with N_c = 2 (Sec. 2.1).  Storages for SU(2): GF_F64_R18
+   and GF_F64_R12 both mean the 4 components in FP64; GF_MIXED_F32_R12 keeps
+   them in FP32 with the same precision policy as for SU(3) (g normalised
+   and applied in FP64, optional FP64 tail); GF_F32_R12 is not available
+   (gf_bind_workspace then fails with GF_E_INVALID).  Every gauge and update
+   type is available; one wavefront per site group.  Only before binding. */
+int gf_set_group(gf_handle h, int nc);
+
 /* Storage (GF_F64_R18, GF_F64_R12, GF_MIXED_F32_R12, GF_F32_R12), reprojection interval
    (inside gf_sweep, reproject the links of every unit still running after
    every `reunit_every` sweeps; 0 = never, Sec. 4.5) and, for mixed storage,
@@ -127,8 +142,9 @@ int gf_workspace_size(gf_handle h, size_t *bytes);
 int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes);
 
 /* Copy time-slices [t0, t0+nt) of instance `inst` from `links` (natural
-   layout, nt*Nx*Ny*Nz*4*18 doubles) into the device storage, converting
-   precision and dropping the third row for 12-real storage.  on_device != 0:
+   layout, nt*Nx*Ny*Nz*4*18 doubles, SU(2): *8) into the device storage,
+   converting precision and dropping the third row for 12-real storage (the
+   second row for SU(2)).  on_device != 0:
    `links` is a device pointer, else a host pointer (staged through the
    workspace).  Enqueued on the handle's stream; returns after the copy. */
 int gf_upload(gf_handle h, int32_t inst, const double *links, int32_t t0, int32_t nt, int on_device);

@@ -493,3 +493,20 @@ def su2_run(U, dims, gauge, update="or", omega=1.7, max_sweeps=1000, tol=1e-12, 
         k += 1
     su2_coulomb_fix_u0(U, dims, G)
     return (0 if not active.any() else 1), list(done)
+
+
+def su2_anneal(U, dims, gauge, T0, T1, nsteps, nmicro=3, seed=0, instance=0, sweep_counter=0, G=None):
+    """The annealing schedule of ``anneal`` for SU(2) (reading R11: T linear
+    from T0 to T1 over nsteps steps, one heatbath sweep then nmicro
+    microcanonical sweeps per step, one random-counter step per sweep);
+    returns the advanced sweep counter."""
+    _check_links2(U, dims)
+    ctr = int(sweep_counter)
+    for k in range(int(nsteps)):
+        T = T0 + (T1 - T0) * k / (nsteps - 1) if nsteps > 1 else T0
+        su2_sweep(U, dims, gauge, HEATBATH, T=T, seed=seed, instance=instance, sweep=ctr, G=G)
+        ctr += 1
+        for _ in range(int(nmicro)):
+            su2_sweep(U, dims, gauge, MICRO, seed=seed, instance=instance, sweep=ctr, G=G)
+            ctr += 1
+    return ctr

@@ -23,7 +23,8 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(os.path.dirname(HERE), "include")]
 
-SOURCES = ["gf_api.cpp", "gf_kernels.hip", "gf_sweep_landau.hip", "gf_sweep_coulomb.hip", "gf_sweep_mag.hip"]
+SOURCES = ["gf_api.cpp", "gf_kernels.hip", "gf_sweep_landau.hip", "gf_sweep_coulomb.hip", "gf_sweep_mag.hip",
+           "gf_sweep_su2.hip"]
 
 
 def _compile(src: str) -> str:

@@ -25,7 +25,7 @@ FORMAT = "gf-checkpoint-1"
 def save(fx, path: str, extra: dict | None = None) -> None:
     """Write the links and sweep indices of every instance of `fx` to `path`."""
     os.makedirs(path, exist_ok=True)
-    state = {"format": FORMAT, "dims": [list(d) for d in fx.dims], "gauge": int(fx.gauge),
+    state = {"format": FORMAT, "dims": [list(d) for d in fx.dims], "group": int(fx.nc), "gauge": int(fx.gauge),
              "storage": int(fx.storage), "sweep_index": [], "extra": extra or {}}
     for k in range(len(fx.dims)):
         np.save(os.path.join(path, "inst%d.npy" % k), fx.download(k), allow_pickle=False)
@@ -36,7 +36,7 @@ def save(fx, path: str, extra: dict | None = None) -> None:
 
 def load(fx, path: str) -> dict:
     """Upload a checkpoint written by `save` into `fx`, which must have the same
-    lattice shapes, gauge and storage; returns the checkpoint's `extra`.
+    lattice shapes, gauge group, gauge and storage; returns the checkpoint's `extra`.
     Raises ValueError (nothing uploaded) on any mismatch."""
     with open(os.path.join(path, "state.json")) as f:
         state = json.load(f)
@@ -44,12 +44,12 @@ def load(fx, path: str) -> dict:
         raise ValueError("not a gauge-fixing checkpoint: %s" % path)
     if [tuple(d) for d in state["dims"]] != list(fx.dims):
         raise ValueError("lattice shapes differ: checkpoint %s, handle %s" % (state["dims"], fx.dims))
-    if state["gauge"] != fx.gauge or state["storage"] != fx.storage:
-        raise ValueError("gauge or storage differ from the checkpoint's")
+    if state.get("group", 3) != fx.nc or state["gauge"] != fx.gauge or state["storage"] != fx.storage:
+        raise ValueError("gauge group, gauge or storage differ from the checkpoint's")
     links = []
     for k, d in enumerate(fx.dims):
         U = np.load(os.path.join(path, "inst%d.npy" % k), allow_pickle=False)
-        want = (int(np.prod(d)), 4, 3, 3, 2)
+        want = (int(np.prod(d)), 4, fx.nc, fx.nc, 2)
         if U.shape != want or U.dtype != np.float64:
             raise ValueError("inst%d.npy holds %s %s, expected float64 %s" % (k, U.dtype, U.shape, want))
         links.append(U)

@@ -59,6 +59,7 @@ struct gf_ctx {
 
     std::vector<InstHost> inst;
     int gauge = GF_LANDAU;
+    int nc = 3;  // gauge group SU(nc)
     int storage = GF_F64_R18;
     int reunit_every = 0;
     double tail_theta = 0.0;
@@ -147,8 +148,10 @@ int fail(gf_ctx *h, int code, const char *fmt, ...) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int nchunks(int storage) {
-    switch (storage) {
+// 16-byte chunks per stored link
+int nchunks(const gf_ctx *h) {
+    if (h->nc == 2) return (h->storage == GF_MIXED_F32_R12) ? 1 : 2;
+    switch (h->storage) {
     case GF_F64_R18:
         return 9;
     case GF_F64_R12:
@@ -158,8 +161,11 @@ int nchunks(int storage) {
     }
 }
 
-int st_code(int storage) {
-    switch (storage) {
+// kernel storage code; SU(2) keeps 4 reals per link in FP64, or in FP32
+// for the mixed policy
+int st_code(const gf_ctx *h) {
+    if (h->nc == 2) return (h->storage == GF_MIXED_F32_R12) ? gfs::ST_SU2_F32 : gfs::ST_SU2_F64;
+    switch (h->storage) {
     case GF_F64_R18:
         return gfs::ST_F64R18;
     case GF_F64_R12:
@@ -170,6 +176,9 @@ int st_code(int storage) {
 }
 
 int ndir(const gf_ctx *h) { return h->gauge == GF_COULOMB ? 3 : 4; }
+
+// reals per site in the natural layout: 4 links of nc x nc complex entries
+int64_t site_reals(const gf_ctx *h) { return 8 * (int64_t)h->nc * h->nc; }
 
 int upd_code(int update) {
     switch (update) {
@@ -194,7 +203,7 @@ T *wsp(gf_ctx *h, size_t off) {
 // compute the layout; with ws == nullptr only the size
 void plan_layout(gf_ctx *h) {
     size_t off = 0;
-    const int nch = nchunks(h->storage);
+    const int nch = nchunks(h);
     int unit = 0;
     for (auto &I : h->inst) {
         I.links_off = (int64_t)off;
@@ -265,7 +274,7 @@ void plan_layout(gf_ctx *h) {
     // staging for host uploads/downloads: up to 32 MiB, at least one site
     int64_t maxV = 0;
     for (auto &I : h->inst) maxV = std::max(maxV, I.V);
-    h->stage_bytes = align256(std::min<size_t>((size_t)32 << 20, (size_t)maxV * 576));
+    h->stage_bytes = align256(std::min<size_t>((size_t)32 << 20, (size_t)maxV * 8 * site_reals(h)));
     h->off_stage = off;
     off += h->stage_bytes;
     h->need_bytes = off;
@@ -309,7 +318,7 @@ int build_tiles(gf_ctx *h, int tab, int W) {
 // heatbath (table 2, measured at 32^4): 1 on FP32 storage, 2 on FP64-12, 4
 // on FP64-18 where available
 int default_W_for(const gf_ctx *h, int tab) {
-    const int st = st_code(h->storage);
+    const int st = st_code(h);
     if (tab == 0) return 1;
     const int upd = (tab == 2) ? gfs::UPD_HEATBATH : gfs::UPD_OR;
     int first = 4;
@@ -334,7 +343,7 @@ int check_unbound(gf_ctx *h) {
 // bytes a unit's sweeps touch: 8 link planes over its half-sites (Coulomb:
 // 6 spatial planes and the 2 accumulator planes)
 int64_t unit_bytes(const gf_ctx *h, int u) {
-    return 8 * (int64_t)h->units[u].n * nchunks(h->storage) * 16;
+    return 8 * (int64_t)h->units[u].n * nchunks(h) * 16;
 }
 
 void build_groups(gf_ctx *h) {
@@ -410,7 +419,7 @@ int drain_timing(gf_ctx *h) {
 
 // one half-sweep of update `upd` (gfs code) at temperature T on all active units
 int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sweep_off, int grp = -1) {
-    const int st = st_code(h->storage);
+    const int st = st_code(h);
     const bool mixed = (h->storage == GF_MIXED_F32_R12);
     const bool single = (h->storage == GF_F32_R12);
     const bool hb = (upd == gfs::UPD_HEATBATH || upd == gfs::UPD_SR);
@@ -476,7 +485,7 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
 // inside gf_sweep (only_active) stopped units are skipped, so they keep the
 // links their stopping check measured
 int launch_reunit_units(gf_ctx *h, bool only_active, int u0, int u1) {
-    const int st = st_code(h->storage);
+    const int st = st_code(h);
     const int32_t *act = only_active ? wsp<int32_t>(h, h->off_active) : nullptr;
     for (auto &I : h->inst) {
         const int a = std::max(u0, (int)I.unit0), b = std::min(u1, (int)(I.unit0 + I.nunits));
@@ -537,15 +546,15 @@ int launch_measure(gf_ctx *h, int with_unitarity, bool decide = false, double to
     a.tiles = wsp<gfs::MTile>(h, h->off_mtiles);
     a.partial = wsp<double>(h, h->off_partial);
     a.with_unitarity = with_unitarity;
-    HIPCHK(h, gfl::measure(h->gauge, st_code(h->storage), (unsigned)h->nmtiles, h->cur, a));
+    HIPCHK(h, gfl::measure(h->gauge, st_code(h), (unsigned)h->nmtiles, h->cur, a));
     if (!decide) {
         HIPCHK(h, gfl::finalize(h->nunits, wsp<gfs::UnitDev>(h, h->off_unit), wsp<double>(h, h->off_partial),
-                                ndir(h), wsp<double>(h, h->off_res), h->cur));
+                                ndir(h), h->nc, wsp<double>(h, h->off_res), h->cur));
         return GF_OK;
     }
     const double tail = (h->storage == GF_MIXED_F32_R12) ? h->tail_theta : 0.0;
     HIPCHK(h, gfl::finalize_decide(h->nunits, wsp<gfs::UnitDev>(h, h->off_unit), wsp<double>(h, h->off_partial),
-                                   ndir(h), wsp<double>(h, h->off_res), wsp<int32_t>(h, h->off_active),
+                                   ndir(h), h->nc, wsp<double>(h, h->off_res), wsp<int32_t>(h, h->off_active),
                                    wsp<int32_t>(h, h->off_fp64), tol, tail, wsp<int32_t>(h, h->off_status),
                                    wsp<uint32_t>(h, h->off_status + 16), h->cur));
     return GF_OK;
@@ -554,7 +563,7 @@ int launch_measure(gf_ctx *h, int with_unitarity, bool decide = false, double to
 
 int coulomb_finish(gf_ctx *h) {
     if (h->gauge != GF_COULOMB) return GF_OK;
-    const int st = st_code(h->storage);
+    const int st = st_code(h);
     for (auto &I : h->inst) {
         const gfs::InstDev d = inst_dev(I);
         HIPCHK(h, gfl::coulomb_fix(st, h->ws, d, h->cur));
@@ -648,6 +657,7 @@ int check_inst(gf_ctx *h, int32_t inst) {
 
 namespace gfl {
 sweep_fn sweep_kernel(int gauge, int upd, int st, int ct_double, int W) {
+    if (gfs::is_su2(st)) return sweep_kernel_su2(gauge, upd, st, ct_double, W);
     if (gauge == gfs::LANDAU) return sweep_kernel_landau(upd, st, ct_double, W);
     if (gauge == gfs::COULOMB) return sweep_kernel_coulomb(upd, st, ct_double, W);
     return sweep_kernel_mag(upd, st, ct_double, W);
@@ -730,6 +740,14 @@ int gf_set_gauge(gf_handle h, int gauge) {
     return GF_OK;
 }
 
+int gf_set_group(gf_handle h, int nc) {
+    int rc = check_unbound(h);
+    if (rc) return rc;
+    if (nc != 2 && nc != 3) return fail(h, GF_E_INVALID, "gauge group SU(%d) is not supported (2 or 3)", nc);
+    h->nc = nc;
+    return GF_OK;
+}
+
 int gf_set_precision(gf_handle h, int storage, int32_t reunit_every, double fp64_tail_theta) {
     int rc = check_unbound(h);
     if (rc) return rc;
@@ -756,6 +774,8 @@ int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes) {
     if (rc) return rc;
     if (h->inst.empty()) return fail(h, GF_E_STATE, "no instance added");
     if (!dev_ptr) return fail(h, GF_E_INVALID, "workspace is NULL");
+    if (h->nc == 2 && h->storage == GF_F32_R12)
+        return fail(h, GF_E_INVALID, "single-precision storage is not built for SU(2) (use mixed or FP64)");
     if (reinterpret_cast<uintptr_t>(dev_ptr) & 255) return fail(h, GF_E_NOMEM, "workspace not 256-byte aligned");
     plan_layout(h);
     if (bytes < h->need_bytes)
@@ -785,7 +805,7 @@ int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes) {
     HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_fp64), h->tail_theta >= 1e300 ? 1 : 0, h->nunits, h->stream));
     HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_sweeps), 0, h->nunits, h->stream));
     HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_status), 0, 8, h->stream));  // status + finalize counter
-    const int st = st_code(h->storage);
+    const int st = st_code(h);
     for (auto &I : h->inst)
         if (I.g_off >= 0) HIPCHK(h, gfl::set_identity(st, h->ws, I.g_off, (int32_t)I.Vh, (int32_t)I.Vp, h->stream));
     if (h->hres) (void)hipHostFree(h->hres);
@@ -817,7 +837,7 @@ static int transfer(gf_handle h, int32_t inst, double *links, int32_t t0, int32_
     const int64_t Vs = I.V / I.n[0];
     const int64_t s0 = (int64_t)t0 * Vs, ns = (int64_t)nt * Vs;
     const gfs::InstDev d = inst_dev(I);
-    const int st = st_code(h->storage);
+    const int st = st_code(h);
     const int reun = (flags & GF_DL_REUNITARISE) ? 1 : 0;
     if (on_device) {
         if (dir == 0)
@@ -827,16 +847,17 @@ static int transfer(gf_handle h, int32_t inst, double *links, int32_t t0, int32_
         HIPCHK(h, hipStreamSynchronize(h->stream));
         return GF_OK;
     }
-    const int64_t per = std::max<int64_t>(1, (int64_t)(h->stage_bytes / 576));
+    const int64_t sr = site_reals(h), sb = 8 * sr;
+    const int64_t per = std::max<int64_t>(1, (int64_t)(h->stage_bytes / sb));
     double *stage = wsp<double>(h, h->off_stage);
     for (int64_t s = 0; s < ns; s += per) {
         const int64_t c = std::min(per, ns - s);
         if (dir == 0) {
-            HIPCHK(h, hipMemcpyAsync(stage, links + s * 72, (size_t)c * 576, hipMemcpyHostToDevice, h->stream));
+            HIPCHK(h, hipMemcpyAsync(stage, links + s * sr, (size_t)(c * sb), hipMemcpyHostToDevice, h->stream));
             HIPCHK(h, gfl::convert_in(st, h->ws, d, stage, s0 + s, c, h->stream));
         } else {
             HIPCHK(h, gfl::convert_out(st, h->ws, d, stage, s0 + s, c, reun, h->stream));
-            HIPCHK(h, hipMemcpyAsync(links + s * 72, stage, (size_t)c * 576, hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipMemcpyAsync(links + s * sr, stage, (size_t)(c * sb), hipMemcpyDeviceToHost, h->stream));
         }
         HIPCHK(h, hipStreamSynchronize(h->stream));
     }
@@ -1135,7 +1156,7 @@ int gf_set_launch(gf_handle h, int lanes_per_site, int block) {
     int rc = check_bound(h);
     if (rc) return rc;
     if (block != 0 && block != gfl::SWEEP_THREADS) return fail(h, GF_E_INVALID, "block %d not available", block);
-    const int st = st_code(h->storage);
+    const int st = st_code(h);
     int set = 0;
     for (int tab = 0; tab < 3; ++tab) {
         const int W = lanes_per_site == 0 ? default_W_for(h, tab) : lanes_per_site;
@@ -1153,7 +1174,7 @@ int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
     int rc = check_bound(h);
     if (rc) return rc;
     if (reps < 1) reps = 1;
-    const int st = st_code(h->storage);
+    const int st = st_code(h);
     rc = drain_timing(h);
     if (rc) return rc;
     hipEvent_t e0 = take_event(h), e1 = take_event(h);

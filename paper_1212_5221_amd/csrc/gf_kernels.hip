@@ -2,6 +2,7 @@
 // reductions in FP64 (Sec. 2.1, Sec. 4.5), per-unit stopping decisions,
 // reprojection to SU(3), layout conversion to and from the natural order,
 // the Coulomb fix-up of the temporal links, and small bookkeeping kernels.
+// The launchers hand the SU(2) storages to their kernels in gf_sweep_su2.hip.
 #include "gf_device.hpp"
 #include "gf_launch.hpp"
 
@@ -198,11 +199,11 @@ __device__ __forceinline__ void decide_units(int nunits, const double *res, int3
 }
 
 // One block per unit: sum the unit's tile partials in a fixed order and
-// normalise: F = sum / (3 NDIR V_u), theta = sum / (3 V_u).  With `decide`,
+// normalise: F = sum / (N_c NDIR V_u), theta = sum / (N_c V_u).  With `decide`,
 // the last block to finish (device-scope fence + counter) also takes the
 // stopping decision over all units and resets the counter.
 __global__ __launch_bounds__(MBLOCK) void k_finalize(const gfs::UnitDev *units, const double *partial, int ndir,
-                                                     double *out /* 4 per unit */, int nunits, int decide,
+                                                     int nc, double *out /* 4 per unit */, int nunits, int decide,
                                                      int32_t *active, int32_t *fp64, double tol, double tail,
                                                      int32_t *status, uint32_t *counter) {
     __shared__ double sh[4];
@@ -221,8 +222,8 @@ __global__ __launch_bounds__(MBLOCK) void k_finalize(const gfs::UnitDev *units, 
     const double bM = block_max(um, sh);
     if (threadIdx.x == 0) {
         const double V = 2.0 * (double)U.n;
-        out[4 * blockIdx.x] = bF / (3.0 * ndir * V);
-        out[4 * blockIdx.x + 1] = bT / (3.0 * V);
+        out[4 * blockIdx.x] = bF / ((double)nc * ndir * V);
+        out[4 * blockIdx.x + 1] = bT / ((double)nc * V);
         out[4 * blockIdx.x + 2] = bU / (4.0 * V);
         out[4 * blockIdx.x + 3] = bM;
     }
@@ -407,22 +408,23 @@ static hipError_t measure_g(int st, unsigned ntiles, hipStream_t s, const gfs::M
 
 hipError_t measure(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a) {
     if (ntiles == 0) return hipSuccess;
+    if (gfs::is_su2(st)) return measure_su2(gauge, st, ntiles, s, a);
     if (gauge == gfs::LANDAU) return measure_g<gfs::LANDAU>(st, ntiles, s, a);
     if (gauge == gfs::COULOMB) return measure_g<gfs::COULOMB>(st, ntiles, s, a);
     return measure_g<gfs::MAG>(st, ntiles, s, a);
 }
 
-hipError_t finalize(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, double *out,
+hipError_t finalize(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, int nc, double *out,
                     hipStream_t s) {
-    k_finalize<<<nunits, MBLOCK, 0, s>>>(units, partial, ndir, out, nunits, 0, nullptr, nullptr, 0.0, 0.0, nullptr,
+    k_finalize<<<nunits, MBLOCK, 0, s>>>(units, partial, ndir, nc, out, nunits, 0, nullptr, nullptr, 0.0, 0.0, nullptr,
                                          nullptr);
     return hipGetLastError();
 }
 
-hipError_t finalize_decide(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, double *out,
-                           int32_t *active, int32_t *fp64, double tol, double tail, int32_t *status,
+hipError_t finalize_decide(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, int nc,
+                           double *out, int32_t *active, int32_t *fp64, double tol, double tail, int32_t *status,
                            uint32_t *counter, hipStream_t s) {
-    k_finalize<<<nunits, MBLOCK, 0, s>>>(units, partial, ndir, out, nunits, 1, active, fp64, tol, tail, status,
+    k_finalize<<<nunits, MBLOCK, 0, s>>>(units, partial, ndir, nc, out, nunits, 1, active, fp64, tol, tail, status,
                                          counter);
     return hipGetLastError();
 }
@@ -444,6 +446,7 @@ hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, in
     const int64_t n = (int64_t)nplanes * nh;
     if (n <= 0) return hipSuccess;
     const int32_t hper = Vh / nunits;
+    if (gfs::is_su2(st)) return reunit_su2(st, ws, off, nplanes, Vp, h_lo, nh, active, unit0, hper, s);
     if (st == gfs::ST_F64R18)
         k_reunit<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vp, h_lo, nh, active, unit0, hper);
     else if (st == gfs::ST_F64R12)
@@ -454,6 +457,7 @@ hipError_t reunit(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vh, in
 }
 
 hipError_t set_identity(int st, char *ws, int64_t off, int32_t Vh, int32_t Vp, hipStream_t s) {
+    if (gfs::is_su2(st)) return set_identity_su2(st, ws, off, Vh, Vp, s);
     const int64_t n = 2 * (int64_t)Vh;
     if (st == gfs::ST_F64R18)
         k_set_identity<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, off, Vh, Vp);
@@ -466,6 +470,7 @@ hipError_t set_identity(int st, char *ws, int64_t off, int32_t Vh, int32_t Vp, h
 
 hipError_t convert_in(int st, char *ws, const gfs::InstDev &I, const double *src, int64_t s0, int64_t ns,
                       hipStream_t s) {
+    if (gfs::is_su2(st)) return convert_in_su2(st, ws, I, src, s0, ns, s);
     const int64_t n = 4 * ns;
     if (st == gfs::ST_F64R18)
         k_convert_in<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, I, src, s0, ns);
@@ -478,6 +483,7 @@ hipError_t convert_in(int st, char *ws, const gfs::InstDev &I, const double *src
 
 hipError_t convert_out(int st, const char *ws, const gfs::InstDev &I, double *dst, int64_t s0, int64_t ns, int reunit,
                        hipStream_t s) {
+    if (gfs::is_su2(st)) return convert_out_su2(st, ws, I, dst, s0, ns, reunit, s);
     const int64_t n = 4 * ns;
     if (st == gfs::ST_F64R18)
         k_convert_out<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, I, dst, s0, ns, reunit);
@@ -489,6 +495,7 @@ hipError_t convert_out(int st, const char *ws, const gfs::InstDev &I, double *ds
 }
 
 hipError_t coulomb_fix(int st, char *ws, const gfs::InstDev &I, hipStream_t s) {
+    if (gfs::is_su2(st)) return coulomb_fix_su2(st, ws, I, s);
     const int64_t n = 2 * (int64_t)I.Vh;
     if (st == gfs::ST_F64R18)
         k_coulomb_fix<gfs::ST_F64R18><<<nblk(n), MBLOCK, 0, s>>>(ws, I);

@@ -15,13 +15,16 @@ sweep_fn sweep_kernel(int gauge, int upd, int st, int ct_double, int W);
 sweep_fn sweep_kernel_landau(int upd, int st, int ct_double, int W);
 sweep_fn sweep_kernel_coulomb(int upd, int st, int ct_double, int W);
 sweep_fn sweep_kernel_mag(int upd, int st, int ct_double, int W);
+// gauge group SU(2) (storages ST_SU2_*; W = 1 only)
+sweep_fn sweep_kernel_su2(int gauge, int upd, int st, int ct_double, int W);
 constexpr int SWEEP_THREADS = 256;
 
 hipError_t measure(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a);
-hipError_t finalize(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, double *out,
+// unit sums -> F = sum / (nc ndir V_u), theta = sum / (nc V_u) (nc: 3 or 2)
+hipError_t finalize(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, int nc, double *out,
                     hipStream_t s);
-hipError_t finalize_decide(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, double *out,
-                           int32_t *active, int32_t *fp64, double tol, double tail, int32_t *status,
+hipError_t finalize_decide(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, int nc,
+                           double *out, int32_t *active, int32_t *fp64, double tol, double tail, int32_t *status,
                            uint32_t *counter, hipStream_t s);
 hipError_t count_sweep(int ninst, const gfs::InstDev *inst, const int32_t *active, int32_t *sweeps_done,
                        uint64_t *sweep_ix, int32_t n, hipStream_t s);
@@ -37,5 +40,16 @@ hipError_t convert_in(int st, char *ws, const gfs::InstDev &I, const double *src
 hipError_t convert_out(int st, const char *ws, const gfs::InstDev &I, double *dst, int64_t s0, int64_t ns, int reunit,
                        hipStream_t s);
 hipError_t coulomb_fix(int st, char *ws, const gfs::InstDev &I, hipStream_t s);
+
+// the same for the SU(2) storages (the functions above dispatch to these)
+hipError_t measure_su2(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a);
+hipError_t reunit_su2(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vp, int32_t h_lo, int32_t nh,
+                      const int32_t *active, int32_t unit0, int32_t hper, hipStream_t s);
+hipError_t set_identity_su2(int st, char *ws, int64_t off, int32_t Vh, int32_t Vp, hipStream_t s);
+hipError_t convert_in_su2(int st, char *ws, const gfs::InstDev &I, const double *src, int64_t s0, int64_t ns,
+                          hipStream_t s);
+hipError_t convert_out_su2(int st, const char *ws, const gfs::InstDev &I, double *dst, int64_t s0, int64_t ns,
+                           int reunit, hipStream_t s);
+hipError_t coulomb_fix_su2(int st, char *ws, const gfs::InstDev &I, hipStream_t s);
 
 }  // namespace gfl

@@ -65,6 +65,7 @@ def load():
     L.gf_last_error.restype = ctypes.c_char_p
     L.gf_add_instance.argtypes = [vp, i32p, i32p]
     L.gf_set_gauge.argtypes = [vp, ci]
+    L.gf_set_group.argtypes = [vp, ci]
     L.gf_set_precision.argtypes = [vp, ci, i32, ctypes.c_double]
     L.gf_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.gf_bind_workspace.argtypes = [vp, vp, ctypes.c_size_t]
@@ -109,7 +110,9 @@ class GaugeFixer:
     """One libgf handle with its instances and the torch-owned workspace."""
 
     def __init__(self, dims_list, gauge="landau", storage="f64r18", reunit_every=0, tail_theta=0.0, device=0,
-                 stream=None):
+                 stream=None, group=3):
+        """group: 3 for SU(3) (links (sites, 4, 3, 3, 2)) or 2 for SU(2)
+        (links (sites, 4, 2, 2, 2))."""
         import torch
 
         self._torch = torch
@@ -131,6 +134,8 @@ class GaugeFixer:
                 self.dims.append(tuple(d))
             self.gauge = _key(GAUGES, gauge)
             self.storage = _key(STORAGES, storage)
+            self.nc = int(group)
+            self._check(self.lib.gf_set_group(self._h, self.nc))
             self._check(self.lib.gf_set_gauge(self._h, self.gauge))
             self._check(self.lib.gf_set_precision(self._h, self.storage, int(reunit_every), float(tail_theta)))
             nbytes = ctypes.c_size_t()
@@ -179,12 +184,21 @@ class GaugeFixer:
         d = self.dims[inst]
         return d[1] * d[2] * d[3]
 
+    @property
+    def link_shape(self):
+        """Shape of one link in the natural layout: (nc, nc, 2)."""
+        return (self.nc, self.nc, 2)
+
+    @property
+    def _site_reals(self):
+        return 8 * self.nc * self.nc
+
     # ------------------------------------------------------------ data
     def upload(self, inst, links, t0=0, nt=None):
         """Links of time-slices [t0, t0+nt): numpy float64 (host) or a CUDA tensor."""
         d = self.dims[inst]
         nt = d[0] - t0 if nt is None else nt
-        n = nt * self._vs(inst) * 72
+        n = nt * self._vs(inst) * self._site_reals
         torch = self._torch
         if isinstance(links, torch.Tensor):
             assert links.dtype == torch.float64 and links.is_contiguous() and links.numel() == n
@@ -200,18 +214,19 @@ class GaugeFixer:
         del keep
 
     def download(self, inst, t0=0, nt=None, reunitarise=False, out=None):
-        """Links of time-slices [t0, t0+nt) as numpy float64 (sites, 4, 3, 3, 2)."""
+        """Links of time-slices [t0, t0+nt) as numpy float64 (sites, 4, nc, nc, 2)."""
         d = self.dims[inst]
         nt = d[0] - t0 if nt is None else nt
         ns = nt * self._vs(inst)
         flags = DL_REUNITARISE if reunitarise else 0
         torch = self._torch
         if out is not None and isinstance(out, torch.Tensor) and out.is_cuda:
-            assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == ns * 72
+            assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == ns * self._site_reals
             self._check(self.lib.gf_download(self._h, inst, ctypes.c_void_p(out.data_ptr()), t0, nt, 1, flags))
             return out
         if out is None:
-            out = np.empty((ns, 4, 3, 3, 2), dtype=np.float64)
+            out = np.empty((ns, 4) + self.link_shape, dtype=np.float64)
+        assert out.dtype == np.float64 and out.flags.c_contiguous and out.size == ns * self._site_reals
         self._check(self.lib.gf_download(self._h, inst, ctypes.c_void_p(out.ctypes.data), t0, nt, 0, flags))
         return out
 

@@ -13,11 +13,12 @@ class HostFixer:
     """Holds what save/load touch on a GaugeFixer: shapes, gauge, storage,
     links per instance and the per-instance sweep index."""
 
-    def __init__(self, dims, gauge=0, storage=2):
+    def __init__(self, dims, gauge=0, storage=2, nc=3):
         self.dims = [tuple(d) for d in dims]
+        self.nc = nc
         self.gauge = gauge
         self.storage = storage
-        self.links = [np.zeros((int(np.prod(d)), 4, 3, 3, 2)) for d in self.dims]
+        self.links = [np.zeros((int(np.prod(d)), 4, nc, nc, 2)) for d in self.dims]
         self.index = [0] * len(self.dims)
 
     def download(self, k):
@@ -64,7 +65,7 @@ def test_files_are_plain_arrays_and_json(tmp_path):
     np.testing.assert_array_equal(np.load(tmp_path / "inst0.npy", allow_pickle=False), a.links[0])
 
 
-@pytest.mark.parametrize("change", ["dims", "count", "gauge", "storage", "format", "array"])
+@pytest.mark.parametrize("change", ["dims", "count", "group", "gauge", "storage", "format", "array"])
 def test_mismatches_are_refused_before_anything_is_uploaded(tmp_path, change):
     dims = [(2, 4, 2, 4), (2, 2, 2, 2)]
     a = _filled(dims, 3)
@@ -74,6 +75,8 @@ def test_mismatches_are_refused_before_anything_is_uploaded(tmp_path, change):
         b = HostFixer([(4, 2, 2, 4), (2, 2, 2, 2)])
     elif change == "count":
         b = HostFixer(dims[:1])
+    elif change == "group":
+        b = HostFixer(dims, nc=2)
     elif change == "gauge":
         b.gauge = 2
     elif change == "storage":
