@@ -53,8 +53,8 @@ BYTES_PER_SITE = {"mixed": 768, "f64r12": 1536, "f64r18": 2304}  # 8 links loade
 COUNTER_SOURCES = ("paper_1212_5221_amd/csrc/gf_sweep.hpp", "paper_1212_5221_amd/csrc/gf_device.hpp",
                    "paper_1212_5221_amd/csrc/gf_shared.hpp", "paper_1212_5221_amd/csrc/gf_sweep_landau.hip",
                    "paper_1212_5221_amd/build.py")
-COUNTER_DIGEST = "8310eaf69405bac7"
-COUNTER_TRAFFIC = {1: 402902713, 2: 402935685, 4: 402951454}
+COUNTER_DIGEST = "ac32ea38c9c8dbf1"
+COUNTER_TRAFFIC = {1: 402902681, 2: 402935727, 4: 402951438}
 
 
 def kernel_digest():
