@@ -155,7 +155,9 @@ def workloads(gf, I):
     * precision study: 32^4 Landau seed 2001 in single, mixed and FP64-12;
     * 32 Gribov copies (8 random gauge copies each of 16^4, 24^4, 40x20^3,
       64x32^3, eps 0.5) fixed to Landau gauge in one batched launch,
-      theta < 1e-12 per copy, FP32-12 storage."""
+      theta < 1e-12 per copy, FP32-12 storage;
+    * gauge group SU(2): 32^4 (eps 0.5, seed 2001) Landau and MAG fixes in
+      mixed and FP64 storage."""
     import torch
     dims = (32, 32, 32, 32)
     inp = torch.from_numpy(I.smooth(dims, 0.7, 4001).reshape(-1)).to("cuda:0")
@@ -288,6 +290,29 @@ def workloads(gf, I):
     print(json.dumps({"workload": "landau-gribov-batch-32-copies", "status": st, "total_s": round(t_all, 3),
                       "site_updates_per_s": su / t_all, "sweeps": done.tolist(), "cache_groups": groups,
                       "best_F": best}), flush=True)
+
+    # gauge group SU(2): 32^4 Landau and MAG fixes (overrelaxation to
+    # theta < 1e-12) in mixed and FP64 storage; the second of two runs is timed
+    d2 = (32, 32, 32, 32)
+    V = int(np.prod(d2))
+    u2 = torch.from_numpy(I.su2_smooth(d2, 0.5, 2001).reshape(-1)).to("cuda:0")
+    runs = []
+    for gauge in ("landau", "mag"):
+        for storage in ("mixed", "f64r18"):
+            fx = gf.GaugeFixer([d2], gauge=gauge, storage=storage, reunit_every=100, group=2)
+            fx.set_overrelax(OMEGA)
+            for _ in range(2):
+                fx.upload(0, u2)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, done = fx.sweep("or", max_sweeps=20000, tol=TOL, check_every=CHECK)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+            F, th = fx.measure(0)
+            fx.close()
+            runs.append({"gauge": gauge, "storage": storage, "status": st, "sweeps": int(done[0]),
+                         "s": round(t, 4), "site_updates_per_s": V * int(done[0]) / t, "F": F, "theta": th})
+    print(json.dumps({"workload": "su2-32^4-eps0.5-seed2001-or-fix", "runs": runs}), flush=True)
 
 
 def kernel_table(gf, I, nsweeps=20):

@@ -265,3 +265,119 @@ def test_long_mixed_run_keeps_links_in_su2():
     fx.close()
     say("unitarity", m, x, "F", F, "theta", th)
     assert x < 1e-5 and np.isfinite(F) and 0.0 < F <= 1.0
+
+
+# ---------------------------------------------------------------- full size
+DIMS32 = (32, 32, 32, 32)
+_FIELDS = {}
+
+
+def field32(seed):
+    """the smooth 32^4 SU(2) field of a seed (generated once per session)"""
+    if seed not in _FIELDS:
+        _FIELDS[seed] = I.su2_smooth(DIMS32, 0.5, seed)
+    return _FIELDS[seed]
+
+
+def _site_links(dims, s):
+    from tests._su import coords, site_index
+    c = list(coords(dims, s))
+    out = [(s, mu) for mu in range(4)]
+    for mu in range(4):
+        b = list(c)
+        b[mu] = (b[mu] - 1) % dims[mu]
+        out.append((site_index(dims, *b), mu))
+    return out
+
+
+@pytest.mark.parametrize("gauge", ["landau", "mag"])
+def test_32x4_halfsweep_sampled_sites(gauge):
+    # the 32^4 lattice in the launch configuration of the kernel table (mixed
+    # storage, FP32 update); the oracle recomputes sampled sites one by one
+    from tests._su import coords
+    say("su2 32^4 half-sweep, sampled sites", gauge)
+    U = field32(2001)
+    fx = fixer([DIMS32], gauge, "mixed")
+    fx.upload(0, U)
+    fx.set_overrelax(1.7)
+    fx.halfsweep("or", 0)
+    out = fx.download(0)
+    fx.close()
+    ref = start("mixed", U)
+    rng = np.random.default_rng(6)
+    sites = []
+    while len(sites) < 256:
+        s = int(rng.integers(0, U.shape[0]))
+        if sum(coords(DIMS32, s)) % 2 == 0:
+            sites.append(s)
+    last = U.shape[0] - 2 + (sum(coords(DIMS32, U.shape[0] - 2)) % 2)
+    sites += [0, last]
+    O.su2_update_sites(ref, DIMS32, gauge, "or", sites, omega=1.7)
+    err = max(float(np.max(np.abs(out[q, mu] - ref[q, mu]))) for s in sites for (q, mu) in _site_links(DIMS32, s))
+    say("max |gpu - oracle| over sampled links", err)
+    assert err < TOL["mixed"]
+
+
+def test_32x4_landau_fix_matches_oracle_F():
+    # a complete mixed-storage Landau fix of the 32^4 SU(2) field: theta below
+    # 1e-12 at the stop, gauge invariants kept, and F within the FP32-orbit
+    # bound of the oracle's F on the downloaded links
+    say("su2 32^4 Landau fix")
+    U = field32(2001)
+    P0 = O.su2_plaquette(start("f64", U), DIMS32)
+    fx = fixer([DIMS32], "landau", "mixed", reunit_every=100)
+    fx.upload(0, U)
+    fx.set_overrelax(1.7)
+    st, done = fx.sweep("or", max_sweeps=20000, tol=1e-12, check_every=20)
+    th_stop = fx.measure(0)[1]
+    F, _ = fx.measure(0)
+    out = fx.download(0)
+    fx.close()
+    say("status", st, "sweeps", done.tolist(), "F", F, "theta", th_stop)
+    assert st == 0 and th_stop < 1e-12
+    Fo, tho = O.su2_measure(out, DIMS32, "landau")
+    assert abs(Fo - F) < 1e-12
+    assert tho < 1e-11
+    assert O.su2_plaquette(out, DIMS32) == pytest.approx(P0, abs=1e-6)
+
+
+# ---------------------------------------------------------------- errors
+def test_group_errors():
+    from paper_1212_5221_amd import gf
+    dims = (4, 4, 4, 4)
+    with pytest.raises(gf.GFError):
+        gf.GaugeFixer([dims], gauge="landau", storage="f64r18", group=4)
+    with pytest.raises(gf.GFError):
+        gf.GaugeFixer([dims], gauge="landau", storage="single", group=2)  # not built for SU(2)
+    fx = fixer([dims], "landau", "f64")
+    with pytest.raises(gf.GFError):
+        fx._check(fx.lib.gf_set_group(fx._h, 3))  # configuration is fixed once bound
+    with pytest.raises(AssertionError):
+        fx.upload(0, np.zeros((256, 4, 3, 3, 2)))  # SU(3) links into an SU(2) handle
+    fx.close()
+
+
+@pytest.mark.parametrize("mode", ["f64", "mixed"])
+def test_checkpoint_resume_su2(mode, tmp_path):
+    from paper_1212_5221_amd import checkpoint
+    dims = (4, 4, 4, 4)
+    say("su2 checkpoint", mode)
+    U = I.su2_hot(dims, 60)
+    a = fixer([dims], "mag", mode)
+    a.upload(0, U)
+    a.set_anneal(1.0, 0.5, 5, nmicro=3, seed=12)
+    a.sweep("anneal")
+    full = a.download(0)
+    a.close()
+    b = fixer([dims], "mag", mode)
+    b.upload(0, U)
+    b.set_anneal(1.0, 0.75, 3, nmicro=3, seed=12)
+    b.sweep("anneal")
+    checkpoint.save(b, str(tmp_path))
+    b.close()
+    c = fixer([dims], "mag", mode)
+    checkpoint.load(c, str(tmp_path))
+    c.set_anneal(0.625, 0.5, 2, nmicro=3, seed=12)
+    c.sweep("anneal")
+    np.testing.assert_array_equal(c.download(0), full)
+    c.close()
