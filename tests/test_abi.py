@@ -10,7 +10,7 @@ from paper_1212_5221_amd import gf
 
 def test_header_declares_the_abi():
     names = gf.header_functions()
-    for must in ("gf_create", "gf_destroy", "gf_last_error", "gf_add_instance", "gf_set_gauge",
+    for must in ("gf_create", "gf_destroy", "gf_last_error", "gf_add_instance", "gf_set_gauge", "gf_set_group",
                  "gf_set_precision", "gf_workspace_size", "gf_bind_workspace", "gf_upload", "gf_download",
                  "gf_set_overrelax", "gf_set_anneal", "gf_sweep", "gf_measure", "gf_measure_timeslices",
                  "gf_unitarity", "gf_reunitarise"):
