@@ -267,6 +267,39 @@ def test_long_mixed_run_keeps_links_in_su2():
     assert x < 1e-5 and np.isfinite(F) and 0.0 < F <= 1.0
 
 
+
+@pytest.mark.parametrize("gauge", ["landau", "coulomb"])
+@pytest.mark.parametrize("what", ["cache groups", "graphs"])
+def test_driver_features_are_bit_identical(gauge, what):
+    # Infinity-Cache groups (one unit per group) and HIP-graph replay of
+    # chunks only reorder or replay the same launches: results and sweep
+    # counts equal the plain run's (mixed storage, reprojection every 5
+    # sweeps and the FP64-update tail included)
+    shapes = [(4, 4, 4, 4), (6, 4, 2, 4), (4, 2, 6, 2)]
+    Us = [I.su2_smooth(d, 0.5, 7301 + k) for k, d in enumerate(shapes)]
+    outs, dones = [], []
+    for on in (False, True):
+        say("su2", what, on, gauge)
+        fx = fixer(shapes, gauge, "mixed", reunit_every=5, tail_theta=1e-9)
+        if what == "cache groups":
+            fx.set_graph(False)
+            fx.set_cache_budget(1 if on else 0)
+            nunits = sum(d[0] for d in shapes) if gauge == "coulomb" else len(shapes)
+            assert fx.cache_groups() == (nunits if on else 1)
+        else:
+            fx.set_graph(on)
+        for k, U in enumerate(Us):
+            fx.upload(k, U)
+        fx.set_overrelax(1.7)
+        st, done = fx.sweep("or", max_sweeps=3000, tol=1e-12, check_every=10)
+        assert st == 0
+        outs.append([fx.download(k) for k in range(len(shapes))])
+        dones.append(done)
+        fx.close()
+    np.testing.assert_array_equal(dones[0], dones[1])
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+
 # ---------------------------------------------------------------- full size
 DIMS32 = (32, 32, 32, 32)
 _FIELDS = {}
