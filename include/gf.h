@@ -1,6 +1,7 @@
 /*
- * gf.h -- C ABI of libgf.so: SU(3) lattice gauge fixing on AMD Instinct
- * MI355X (gfx950) by checkerboard overrelaxation and simulated annealing.
+ * gf.h -- C ABI of libgf.so: SU(3) and SU(2) lattice gauge fixing on AMD
+ * Instinct MI355X (gfx950) by checkerboard overrelaxation and simulated
+ * annealing.
  *
  * Method: M. Schroeck and H. Vogt, "Coulomb, Landau and Maximally Abelian
  * Gauge Fixing in Lattice QCD with Multi-GPUs", arXiv:1212.5221.
@@ -194,8 +195,9 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
 int gf_halfsweep(gf_handle h, int update, int parity);
 
 /* F and theta of instance `inst` (Sec. 2.1) reduced in FP64 at the current
-   state; Coulomb: averages over the time-slices.  GF_E_NONFINITE if either is
-   not finite. */
+   state, normalised with the N_c of the gauge group (3 or 2); MAG: F is the
+   practical form (1/(N_c N_d V)) sum |U_ii|^2.  Coulomb: averages over the
+   time-slices.  GF_E_NONFINITE if either is not finite. */
 int gf_measure(gf_handle h, int32_t inst, double *F, double *theta);
 
 /* Coulomb: per time-slice F_t, theta_t (Nt values each). */
@@ -204,7 +206,8 @@ int gf_measure_timeslices(gf_handle h, int32_t inst, double *F_t, double *theta_
 /* Mean and maximum of |1 - det U| over the links of `inst` (Sec. 4.5). */
 int gf_unitarity(gf_handle h, int32_t inst, double *mean, double *max);
 
-/* Reproject every link (and the Coulomb accumulator) to SU(3) in FP64. */
+/* Reproject every link (and the Coulomb accumulator) to SU(3) in FP64
+   (SU(2): normalise the 4 components). */
 int gf_reunitarise(gf_handle h);
 
 /* Global sweep index of instance `inst`, the random-stream counter
