@@ -351,19 +351,24 @@ def test_32x4_halfsweep_sampled_sites(gauge):
     assert err < TOL["mixed"]
 
 
-def test_32x4_landau_fix_matches_oracle_F():
-    # a complete mixed-storage Landau fix of the 32^4 SU(2) field: theta below
-    # 1e-12 at the stop, gauge invariants kept, and F within the FP32-orbit
-    # bound of the oracle's F on the downloaded links
-    say("su2 32^4 Landau fix")
+@pytest.mark.parametrize("mode", ["mixed", "f64"])
+def test_32x4_landau_fix_matches_oracle_F(mode):
+    # a complete Landau fix of the 32^4 SU(2) field: theta below 1e-12 at the
+    # stop, gauge invariants kept, F equal to the oracle's F on the
+    # downloaded links, and F against the oracle's own fix of the same input
+    # (tests/golden/su2_landau_oracle.json, written by a script that calls
+    # only the oracle): FP64 the same sweep count and F to 1e-12; mixed F to
+    # the 1e-9 relative tolerance of the FP32-storage path
+    import json
+    import os
+    say("su2 32^4 Landau fix", mode)
     U = field32(2001)
     P0 = O.su2_plaquette(start("f64", U), DIMS32)
-    fx = fixer([DIMS32], "landau", "mixed", reunit_every=100)
+    fx = fixer([DIMS32], "landau", mode, reunit_every=100)
     fx.upload(0, U)
     fx.set_overrelax(1.7)
     st, done = fx.sweep("or", max_sweeps=20000, tol=1e-12, check_every=20)
-    th_stop = fx.measure(0)[1]
-    F, _ = fx.measure(0)
+    F, th_stop = fx.measure(0)
     out = fx.download(0)
     fx.close()
     say("status", st, "sweeps", done.tolist(), "F", F, "theta", th_stop)
@@ -371,7 +376,14 @@ def test_32x4_landau_fix_matches_oracle_F():
     Fo, tho = O.su2_measure(out, DIMS32, "landau")
     assert abs(Fo - F) < 1e-12
     assert tho < 1e-11
-    assert O.su2_plaquette(out, DIMS32) == pytest.approx(P0, abs=1e-6)
+    assert O.su2_plaquette(out, DIMS32) == pytest.approx(P0, abs=1e-6 if mode == "mixed" else 1e-12)
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "su2_landau_oracle.json")))["2001"]
+    say("oracle fix: sweeps", g["sweeps"], "F", g["F"], "rel dF", abs(F - g["F"]) / g["F"])
+    if mode == "f64":
+        assert int(done[0]) == g["sweeps"]
+        assert abs(F - g["F"]) < 1e-12
+    else:
+        assert abs(F - g["F"]) < 1e-9 * g["F"]
 
 
 # ---------------------------------------------------------------- errors
