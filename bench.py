@@ -157,7 +157,8 @@ def workloads(gf, I):
       64x32^3, eps 0.5) fixed to Landau gauge in one batched launch,
       theta < 1e-12 per copy, FP32-12 storage;
     * gauge group SU(2): 32^4 (eps 0.5, seed 2001) Landau and MAG fixes in
-      mixed and FP64 storage."""
+      mixed and FP64 storage, and MAG annealing of a hot 32^4 field then
+      overrelaxation."""
     import torch
     dims = (32, 32, 32, 32)
     inp = torch.from_numpy(I.smooth(dims, 0.7, 4001).reshape(-1)).to("cuda:0")
@@ -313,6 +314,29 @@ def workloads(gf, I):
             runs.append({"gauge": gauge, "storage": storage, "status": st, "sweeps": int(done[0]),
                          "s": round(t, 4), "site_updates_per_s": V * int(done[0]) / t, "F": F, "theta": th})
     print(json.dumps({"workload": "su2-32^4-eps0.5-seed2001-or-fix", "runs": runs}), flush=True)
+    # SU(2) MAG on a hot 32^4 field: annealing T 1.5 -> 0.01 over 1000 steps
+    # (heatbath + 3 microcanonical sweeps each), then overrelaxation to
+    # theta < 1e-12, mixed storage
+    hot = torch.from_numpy(I.su2_hot(d2, 4011).reshape(-1)).to("cuda:0")
+    fx = gf.GaugeFixer([d2], gauge="mag", storage="mixed", reunit_every=100, group=2)
+    fx.set_overrelax(OMEGA)
+    fx.upload(0, hot)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fx.set_anneal(1.5, 0.01, 1000, nmicro=3, seed=4012)
+    fx.sweep("anneal")
+    torch.cuda.synchronize()
+    t_sa = time.perf_counter() - t0
+    F_sa, _ = fx.measure(0)
+    st, done = fx.sweep("or", max_sweeps=100000, tol=TOL, check_every=CHECK)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    F, th = fx.measure(0)
+    m, x = fx.unitarity(0)
+    fx.close()
+    print(json.dumps({"workload": "su2-mag-32^4-hot-anneal1000-T1.5to0.01-then-or", "anneal_s": round(t_sa, 4),
+                      "F_after_anneal": F_sa, "or_status": st, "or_sweeps": int(done[0]),
+                      "total_s": round(t_all, 4), "F": F, "theta": th, "unitarity_max": x}), flush=True)
 
 
 def kernel_table(gf, I, nsweeps=20):
