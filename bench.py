@@ -101,7 +101,8 @@ def one_fix(fx, inp):
 
 def cpu_baseline(budget_s=12.0):
     """The oracle (FP64, OpenMP over the host cores) on a bounded sample: OR
-    sweeps of the seed-2001 configuration until about budget_s seconds."""
+    sweeps of the seed-2001 configuration until about budget_s seconds; then
+    its rate on one core over about 6 s."""
     import oracle as O
     from paper_1212_5221_amd import inputs as I
     U = I.smooth(DIMS, EPS, SEEDS[0])
@@ -116,8 +117,29 @@ def cpu_baseline(budget_s=12.0):
             break
     el = time.time() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": V * n / el, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
-            "sample": "%d Landau OR sweeps (omega 1.7) of the 32^4 seed-2001 configuration, FP64, %.1f s" % (n, el)}
+    out = {"value": V * n / el, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
+           "sample": "%d Landau OR sweeps (omega 1.7) of the 32^4 seed-2001 configuration, FP64, %.1f s" % (n, el)}
+    # the same on one core (OpenMP limited to one thread for these sweeps)
+    try:
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+        before = gomp.omp_get_max_threads()
+        gomp.omp_set_num_threads(1)
+        try:
+            n1 = 0
+            t0 = time.time()
+            while True:
+                O.sweep(U, DIMS, "landau", "or", omega=OMEGA)
+                n1 += 1
+                if time.time() - t0 > 6.0 and n1 >= 2:
+                    break
+            el1 = time.time() - t0
+        finally:
+            gomp.omp_set_num_threads(before)
+        out["one_core"] = {"value": V * n1 / el1, "sample": "%d sweeps, %.1f s" % (n1, el1)}
+    except OSError:
+        pass
+    return out
 
 
 def copy_ceiling(torch, nbytes, reps=20):
