@@ -9,7 +9,9 @@ tests/test_oracle_iteration.py), so GPU and oracle chains are compared over
 one annealing step, where rounding differences stay below 1e-8, and longer
 chains by invariants and convergence.
 Mixed storage cannot follow the FP64 chain (FP32 rounding changes the
-samples), so at full size (32^4 MAG, the annealing workload) it is checked by
+samples), so its heatbath and stochastic-relaxation half-sweeps are each
+recomputed by the oracle from the state the GPU stored before them, and at
+full size (32^4 MAG, the annealing workload) the chain is checked by
 properties and by one overrelaxation half-sweep recomputed by the oracle on
 sampled sites of the annealed state.
 """
@@ -258,3 +260,32 @@ def test_checkpoint_files_resume_bit_identically(storage, tmp_path):
     np.testing.assert_array_equal(c.download(0), full[0])
     np.testing.assert_array_equal(c.download(1), full[1])
     c.close()
+
+
+@pytest.mark.parametrize("gauge", ["landau", "coulomb", "mag"])
+@pytest.mark.parametrize("update", ["heatbath", "sr"])
+def test_mixed_random_halfsweeps_match_oracle_from_the_stored_state(gauge, update):
+    # Mixed storage cannot follow the FP64 chain, so each half-sweep of the
+    # heatbath and stochastic-relaxation kernels on FP32-12 storage (update
+    # computed in FP64) is recomputed by the oracle from the state the GPU
+    # stored before it (same seed, temperature and sweep index).  Both sides
+    # then start from the same links; the GPU's result differs only by the
+    # FP32 rounding of the stored rows and the first-order renormalisation of
+    # the forward links before it, each a few ulp(1) = 6e-8: bound 1e-6.
+    dims = (4, 4, 6, 4)
+    say("mixed", update, "half-sweeps from the stored state", gauge)
+    fx = fixer([dims], gauge, "mixed")
+    fx.upload(0, I.smooth(dims, 0.7, 4101))
+    fx.set_seed(41)
+    fx.set_temperature(0.8)
+    fx.set_stochastic(0.5)
+    for k in range(3):
+        fx.set_sweep_index(0, k)
+        for parity in (0, 1):
+            S = fx.download(0)
+            fx.halfsweep(update, parity)
+            out = fx.download(0)
+            O.halfsweep(S, dims, gauge, update, parity, omega=1.0, T=0.8, p_sr=0.5, seed=41, instance=0, sweep=k)
+            err = np.max(np.abs(out - S))
+            assert err < 1e-6, (k, parity, err)
+    fx.close()
