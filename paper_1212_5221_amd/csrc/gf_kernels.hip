@@ -5,35 +5,9 @@
 // The launchers hand the SU(2) storages to their kernels in gf_sweep_su2.hip.
 #include "gf_device.hpp"
 #include "gf_launch.hpp"
+#include "gf_reduce.hpp"
 
 namespace gfd {
-
-constexpr int MBLOCK = 256;
-
-// sum over a 256-thread block, result valid in thread 0 (fixed order)
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-    return r;
-}
-
-__device__ __forceinline__ double block_max(double v, double *sh) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
-    return r;
-}
 
 // traceless part of (K - K^dag)/(2i): sum |.|^2
 __device__ __forceinline__ double delta_norm2(const M3<double> &K) {

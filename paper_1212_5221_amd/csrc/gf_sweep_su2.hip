@@ -10,6 +10,7 @@
 // of the active parity reads and writes its 8 (Coulomb 6) links once:
 // 256 bytes (FP32) or 512 bytes (FP64) of traffic per site update.
 #include "gf_launch.hpp"
+#include "gf_reduce.hpp"
 #include "gf_sweep.hpp"
 
 namespace gfd {
@@ -190,32 +191,6 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep_su2(gfs::SweepArgs a) {
 }
 
 // ---------------------------------------------------------------- measures
-constexpr int MBLOCK2 = 256;
-
-__device__ __forceinline__ double block_sum2(double v, double *sh) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-    return r;
-}
-
-__device__ __forceinline__ double block_max2(double v, double *sh) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
-    return r;
-}
-
 // the 2x2 complex matrix of a Cayley-Klein 4-vector
 __device__ __forceinline__ void ck_matrix(const Q4<double> &u, cx<double> m[2][2]) {
     m[0][0] = cmk(u.v[0], u.v[3]);
@@ -230,11 +205,11 @@ __device__ __forceinline__ void ck_matrix(const Q4<double> &u, cx<double> m[2][2
 // d = sum_mu u_vec(x) - u_vec(x - mu), so 2 |d|^2; MAG |X_01|^2 with
 // X = sum_mu U sigma_3 U^dag + U'^dag sigma_3 U', Sec. 2.1.2), and |1 - det U|.
 template <int GAUGE, int ST>
-__global__ __launch_bounds__(MBLOCK2) void k_measure_su2(gfs::MeasureArgs a) {
+__global__ __launch_bounds__(MBLOCK) void k_measure_su2(gfs::MeasureArgs a) {
     typedef Store<ST> SD;
     constexpr int NDIR = (GAUGE == gfs::COULOMB) ? 3 : 4;
     constexpr int MU0 = (GAUGE == gfs::COULOMB) ? 1 : 0;
-    static_assert(gfs::MTILE_SITES * 2 == MBLOCK2, "a measure block covers its tile in both parities");
+    static_assert(gfs::MTILE_SITES * 2 == MBLOCK, "a measure block covers its tile in both parities");
     __shared__ double sh[4];
     const int tix = xcd_tile(blockIdx.x, gridDim.x);
     const gfs::MTile tl = a.tiles[tix];
@@ -289,12 +264,12 @@ __global__ __launch_bounds__(MBLOCK2) void k_measure_su2(gfs::MeasureArgs a) {
         }
     }
     if (!valid) F = th = us = um = 0.0;
-    const double bF = block_sum2(F, sh);
-    const double bT = block_sum2(th, sh);
+    const double bF = block_sum(F, sh);
+    const double bT = block_sum(th, sh);
     double bU = 0.0, bM = 0.0;
     if (a.with_unitarity) {
-        bU = block_sum2(us, sh);
-        bM = block_max2(um, sh);
+        bU = block_sum(us, sh);
+        bM = block_max(um, sh);
     }
     if (threadIdx.x == 0) {
         double *o = a.partial + 4 * (int64_t)tix;
@@ -309,11 +284,11 @@ __global__ __launch_bounds__(MBLOCK2) void k_measure_su2(gfs::MeasureArgs a) {
 // normalise the 4-vector of every (plane, half-site) of the region; stopped
 // units are left as they are
 template <int ST>
-__global__ __launch_bounds__(MBLOCK2) void k_reunit_su2(char *ws, int64_t off, int32_t nplanes, int32_t Vp,
+__global__ __launch_bounds__(MBLOCK) void k_reunit_su2(char *ws, int64_t off, int32_t nplanes, int32_t Vp,
                                                         int32_t h_lo, int32_t nh, const int32_t *active,
                                                         int32_t unit0, int32_t hper) {
     typedef Store<ST> SD;
-    const int64_t idx = (int64_t)blockIdx.x * MBLOCK2 + threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
     if (idx >= (int64_t)nplanes * nh) return;
     const int32_t pl = (int32_t)(idx / nh), h = h_lo + (int32_t)(idx - (int64_t)pl * nh);
     if (active && !active[unit0 + h / hper]) return;
@@ -328,9 +303,9 @@ __global__ __launch_bounds__(MBLOCK2) void k_reunit_su2(char *ws, int64_t off, i
 }
 
 template <int ST>
-__global__ __launch_bounds__(MBLOCK2) void k_set_identity_su2(char *ws, int64_t off, int32_t Vh, int32_t Vp) {
+__global__ __launch_bounds__(MBLOCK) void k_set_identity_su2(char *ws, int64_t off, int32_t Vh, int32_t Vp) {
     typedef Store<ST> SD;
-    const int64_t idx = (int64_t)blockIdx.x * MBLOCK2 + threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
     if (idx >= 2 * (int64_t)Vh) return;
     const int32_t pl = (int32_t)(idx / Vh), h = (int32_t)(idx - (int64_t)pl * Vh);
     typename SD::V *base = reinterpret_cast<typename SD::V *>(ws + off) + (int64_t)pl * SD::NCH * Vp;
@@ -353,10 +328,10 @@ __device__ __forceinline__ void natural_site(const gfs::InstDev &I, int64_t site
 }
 
 template <int ST>
-__global__ __launch_bounds__(MBLOCK2) void k_convert_in_su2(char *ws, gfs::InstDev I, const double *src, int64_t s0,
+__global__ __launch_bounds__(MBLOCK) void k_convert_in_su2(char *ws, gfs::InstDev I, const double *src, int64_t s0,
                                                             int64_t ns) {
     typedef Store<ST> SD;
-    const int64_t idx = (int64_t)blockIdx.x * MBLOCK2 + threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
     if (idx >= ns * 4) return;
     const int64_t k = idx >> 2;
     const int mu = (int)(idx & 3);
@@ -372,10 +347,10 @@ __global__ __launch_bounds__(MBLOCK2) void k_convert_in_su2(char *ws, gfs::InstD
 }
 
 template <int ST>
-__global__ __launch_bounds__(MBLOCK2) void k_convert_out_su2(const char *ws, gfs::InstDev I, double *dst, int64_t s0,
+__global__ __launch_bounds__(MBLOCK) void k_convert_out_su2(const char *ws, gfs::InstDev I, double *dst, int64_t s0,
                                                              int64_t ns, int reunit) {
     typedef Store<ST> SD;
-    const int64_t idx = (int64_t)blockIdx.x * MBLOCK2 + threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
     if (idx >= ns * 4) return;
     const int64_t k = idx >> 2;
     const int mu = (int)(idx & 3);
@@ -399,9 +374,9 @@ __global__ __launch_bounds__(MBLOCK2) void k_convert_out_su2(const char *ws, gfs
 
 // U_0(x) <- G(x) U_0(x) G(x + 0)^dag (Coulomb, Sec. 5)
 template <int ST>
-__global__ __launch_bounds__(MBLOCK2) void k_coulomb_fix_su2(char *ws, gfs::InstDev I) {
+__global__ __launch_bounds__(MBLOCK) void k_coulomb_fix_su2(char *ws, gfs::InstDev I) {
     typedef Store<ST> SD;
-    const int64_t idx = (int64_t)blockIdx.x * MBLOCK2 + threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * MBLOCK + threadIdx.x;
     if (idx >= 2 * (int64_t)I.Vh) return;
     const int p = (int)(idx / I.Vh);
     const int32_t h = (int32_t)(idx - (int64_t)p * I.Vh);
@@ -453,14 +428,14 @@ sweep_fn sweep_kernel_su2(int gauge, int upd, int st, int ctd, int W) {
     return su2_variant<gfs::MAG>(upd, st, ctd);
 }
 
-static inline unsigned nblk2(int64_t n) { return (unsigned)((n + MBLOCK2 - 1) / MBLOCK2); }
+static inline unsigned nblk_su2(int64_t n) { return (unsigned)((n + MBLOCK - 1) / MBLOCK); }
 
 template <int G>
 static void measure_su2_g(int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a) {
     if (st == gfs::ST_SU2_F64)
-        k_measure_su2<G, gfs::ST_SU2_F64><<<ntiles, MBLOCK2, 0, s>>>(a);
+        k_measure_su2<G, gfs::ST_SU2_F64><<<ntiles, MBLOCK, 0, s>>>(a);
     else
-        k_measure_su2<G, gfs::ST_SU2_F32><<<ntiles, MBLOCK2, 0, s>>>(a);
+        k_measure_su2<G, gfs::ST_SU2_F32><<<ntiles, MBLOCK, 0, s>>>(a);
 }
 
 hipError_t measure_su2(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a) {
@@ -478,18 +453,18 @@ hipError_t reunit_su2(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vp
                       const int32_t *active, int32_t unit0, int32_t hper, hipStream_t s) {
     const int64_t n = (int64_t)nplanes * nh;
     if (st == gfs::ST_SU2_F64)
-        k_reunit_su2<gfs::ST_SU2_F64><<<nblk2(n), MBLOCK2, 0, s>>>(ws, off, nplanes, Vp, h_lo, nh, active, unit0, hper);
+        k_reunit_su2<gfs::ST_SU2_F64><<<nblk_su2(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vp, h_lo, nh, active, unit0, hper);
     else
-        k_reunit_su2<gfs::ST_SU2_F32><<<nblk2(n), MBLOCK2, 0, s>>>(ws, off, nplanes, Vp, h_lo, nh, active, unit0, hper);
+        k_reunit_su2<gfs::ST_SU2_F32><<<nblk_su2(n), MBLOCK, 0, s>>>(ws, off, nplanes, Vp, h_lo, nh, active, unit0, hper);
     return hipGetLastError();
 }
 
 hipError_t set_identity_su2(int st, char *ws, int64_t off, int32_t Vh, int32_t Vp, hipStream_t s) {
     const int64_t n = 2 * (int64_t)Vh;
     if (st == gfs::ST_SU2_F64)
-        k_set_identity_su2<gfs::ST_SU2_F64><<<nblk2(n), MBLOCK2, 0, s>>>(ws, off, Vh, Vp);
+        k_set_identity_su2<gfs::ST_SU2_F64><<<nblk_su2(n), MBLOCK, 0, s>>>(ws, off, Vh, Vp);
     else
-        k_set_identity_su2<gfs::ST_SU2_F32><<<nblk2(n), MBLOCK2, 0, s>>>(ws, off, Vh, Vp);
+        k_set_identity_su2<gfs::ST_SU2_F32><<<nblk_su2(n), MBLOCK, 0, s>>>(ws, off, Vh, Vp);
     return hipGetLastError();
 }
 
@@ -497,9 +472,9 @@ hipError_t convert_in_su2(int st, char *ws, const gfs::InstDev &I, const double 
                           hipStream_t s) {
     const int64_t n = 4 * ns;
     if (st == gfs::ST_SU2_F64)
-        k_convert_in_su2<gfs::ST_SU2_F64><<<nblk2(n), MBLOCK2, 0, s>>>(ws, I, src, s0, ns);
+        k_convert_in_su2<gfs::ST_SU2_F64><<<nblk_su2(n), MBLOCK, 0, s>>>(ws, I, src, s0, ns);
     else
-        k_convert_in_su2<gfs::ST_SU2_F32><<<nblk2(n), MBLOCK2, 0, s>>>(ws, I, src, s0, ns);
+        k_convert_in_su2<gfs::ST_SU2_F32><<<nblk_su2(n), MBLOCK, 0, s>>>(ws, I, src, s0, ns);
     return hipGetLastError();
 }
 
@@ -507,18 +482,18 @@ hipError_t convert_out_su2(int st, const char *ws, const gfs::InstDev &I, double
                            int reunit, hipStream_t s) {
     const int64_t n = 4 * ns;
     if (st == gfs::ST_SU2_F64)
-        k_convert_out_su2<gfs::ST_SU2_F64><<<nblk2(n), MBLOCK2, 0, s>>>(ws, I, dst, s0, ns, reunit);
+        k_convert_out_su2<gfs::ST_SU2_F64><<<nblk_su2(n), MBLOCK, 0, s>>>(ws, I, dst, s0, ns, reunit);
     else
-        k_convert_out_su2<gfs::ST_SU2_F32><<<nblk2(n), MBLOCK2, 0, s>>>(ws, I, dst, s0, ns, reunit);
+        k_convert_out_su2<gfs::ST_SU2_F32><<<nblk_su2(n), MBLOCK, 0, s>>>(ws, I, dst, s0, ns, reunit);
     return hipGetLastError();
 }
 
 hipError_t coulomb_fix_su2(int st, char *ws, const gfs::InstDev &I, hipStream_t s) {
     const int64_t n = 2 * (int64_t)I.Vh;
     if (st == gfs::ST_SU2_F64)
-        k_coulomb_fix_su2<gfs::ST_SU2_F64><<<nblk2(n), MBLOCK2, 0, s>>>(ws, I);
+        k_coulomb_fix_su2<gfs::ST_SU2_F64><<<nblk_su2(n), MBLOCK, 0, s>>>(ws, I);
     else
-        k_coulomb_fix_su2<gfs::ST_SU2_F32><<<nblk2(n), MBLOCK2, 0, s>>>(ws, I);
+        k_coulomb_fix_su2<gfs::ST_SU2_F32><<<nblk_su2(n), MBLOCK, 0, s>>>(ws, I);
     return hipGetLastError();
 }
 
