@@ -445,11 +445,14 @@ def main():
                     help="only time the half-sweep of every gauge, storage and update on 32^4 (one JSON line each)")
     ap.add_argument("--profile-sweeps", type=int, default=0,
                     help="only run this many OR sweeps of the workload (for profiler counter runs)")
+    ap.add_argument("--profile-su2", type=int, default=0,
+                    help="only run this many OR sweeps of the 32^4 SU(2) Landau field, mixed storage "
+                         "(for profiler counter runs)")
     args = ap.parse_args()
     if args.fp64_tail is not None:
         TAIL = args.fp64_tail
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the gauge-fixing path is not sharded across GPUs); "
+        print("bench.py: measures one GPU only (the gauge-fixing path is not sharded across GPUs); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
@@ -470,6 +473,18 @@ def main():
         return
     if args.workloads:
         workloads(gf, I)
+        return
+    if args.profile_su2:
+        # 32^4 SU(2), eps 0.5, seed 2001: one upload, then the sweeps in one
+        # chunk; a half-sweep moves 256 B per site update over V/2 sites
+        u2 = I.su2_smooth(DIMS, EPS, SEEDS[0])
+        fx = gf.GaugeFixer([DIMS], gauge="landau", storage="mixed", reunit_every=0, group=2)
+        fx.upload(0, u2)
+        fx.set_overrelax(OMEGA)
+        fx.sweep("or", max_sweeps=args.profile_su2, tol=0.0, check_every=args.profile_su2)
+        fx.close()
+        print(json.dumps({"profile_su2_sweeps": args.profile_su2, "bytes_per_launch": 256 * int(np.prod(DIMS)) // 2}),
+              flush=True)
         return
     if args.profile_sweeps:
         # a fixed number of OR sweeps of seed 2001 in the benchmark's launch
