@@ -300,6 +300,23 @@ def test_driver_features_are_bit_identical(gauge, what):
     for a, b in zip(outs[0], outs[1]):
         np.testing.assert_array_equal(a, b)
 
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (2, 4, 2, 2), (4, 2, 2, 6)])
+@pytest.mark.parametrize("gauge", GAUGES)
+def test_smallest_lattices(dims, gauge):
+    # extent 2: the forward and backward neighbours in that direction are the
+    # same site, so both links of the pair are updated by one site
+    say("su2 smallest", dims, gauge)
+    out, ref = _one_sweep(gauge, "or", "f64", dims, 70)
+    assert np.max(np.abs(out - ref)) < 1e-12
+    fx = fixer([dims], gauge, "f64")
+    U = I.su2_smooth(dims, 0.5, 71)
+    fx.upload(0, U)
+    st, done = fx.sweep("or", max_sweeps=0, tol=1e-12, check_every=1)
+    assert np.all(done == 0)
+    np.testing.assert_array_equal(fx.download(0), start("f64", U))
+    fx.close()
+
 # ---------------------------------------------------------------- full size
 DIMS32 = (32, 32, 32, 32)
 _FIELDS = {}
