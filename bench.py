@@ -53,8 +53,8 @@ BYTES_PER_SITE = {"mixed": 768, "f64r12": 1536, "f64r18": 2304}  # 8 links loade
 COUNTER_SOURCES = ("paper_1212_5221_amd/csrc/gf_sweep.hpp", "paper_1212_5221_amd/csrc/gf_device.hpp",
                    "paper_1212_5221_amd/csrc/gf_shared.hpp", "paper_1212_5221_amd/csrc/gf_sweep_landau.hip",
                    "paper_1212_5221_amd/build.py")
-COUNTER_DIGEST = "ac32ea38c9c8dbf1"
-COUNTER_TRAFFIC = {1: 402902681, 2: 402935727, 4: 402951438}
+COUNTER_DIGEST = "df96ddbb5cf1a0ce"
+COUNTER_TRAFFIC = {1: 402902697, 2: 402935656, 4: 402951422}
 
 
 def kernel_digest():
@@ -395,12 +395,12 @@ def kernel_table(gf, I, nsweeps=20):
                                   "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}), flush=True)
     # gauge group SU(2): 4 reals per link (16 bytes FP32, 32 bytes FP64)
     U2 = I.su2_smooth(DIMS, EPS, SEEDS[0])
-    link2 = {"mixed": 16, "f64r18": 32}
+    link2 = {"mixed": 16, "single": 16, "f64r18": 32}
     for gauge in ("landau", "coulomb", "mag"):
         nl = 6 if gauge == "coulomb" else 8
-        for storage in ("mixed", "f64r18"):
+        for storage in ("mixed", "single", "f64r18"):
             bps = 2 * nl * link2[storage] + (2 * link2[storage] if gauge == "coulomb" else 0)
-            for upd in ("or", "heatbath"):
+            for upd in (("or",) if storage == "single" else ("or", "heatbath")):
                 fx = gf.GaugeFixer([DIMS], gauge=gauge, storage=storage, reunit_every=0, tail_theta=0.0, group=2)
                 fx.set_cache_budget(0)
                 fx.upload(0, U2)

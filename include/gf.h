@@ -114,8 +114,8 @@ int gf_set_gauge(gf_handle h, int gauge);
    are normalised with N_c = 2 (Sec. 2.1).  Storages for SU(2): GF_F64_R18
    and GF_F64_R12 both mean the 4 components in FP64; GF_MIXED_F32_R12 keeps
    them in FP32 with the same precision policy as for SU(3) (g normalised
-   and applied in FP64, optional FP64 tail); GF_F32_R12 is not available
-   (gf_bind_workspace then fails with GF_E_INVALID).  Every gauge and update
+   and applied in FP64, optional FP64 tail); GF_F32_R12 keeps them in FP32
+   and applies g in FP32 too (single precision).  Every gauge and update
    type is available; one wavefront per site group.  Only before binding. */
 int gf_set_group(gf_handle h, int nc);
 

@@ -150,7 +150,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // 16-byte chunks per stored link
 int nchunks(const gf_ctx *h) {
-    if (h->nc == 2) return (h->storage == GF_MIXED_F32_R12) ? 1 : 2;
+    if (h->nc == 2) return (h->storage == GF_MIXED_F32_R12 || h->storage == GF_F32_R12) ? 1 : 2;
     switch (h->storage) {
     case GF_F64_R18:
         return 9;
@@ -162,9 +162,10 @@ int nchunks(const gf_ctx *h) {
 }
 
 // kernel storage code; SU(2) keeps 4 reals per link in FP64, or in FP32
-// for the mixed policy
+// for the mixed and single-precision policies
 int st_code(const gf_ctx *h) {
-    if (h->nc == 2) return (h->storage == GF_MIXED_F32_R12) ? gfs::ST_SU2_F32 : gfs::ST_SU2_F64;
+    if (h->nc == 2)
+        return (h->storage == GF_MIXED_F32_R12 || h->storage == GF_F32_R12) ? gfs::ST_SU2_F32 : gfs::ST_SU2_F64;
     switch (h->storage) {
     case GF_F64_R18:
         return gfs::ST_F64R18;
@@ -453,7 +454,7 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
     for (int k = 0; k < nl; ++k) {
         const int ctd = launches[k].ctd, tab = launches[k].tab;
         // single precision: the FP32-update kernels that also apply G in FP32
-        const int kst = (single && ctd == 0) ? (int)gfs::ST_F32R12_SP : st;
+        const int kst = (single && ctd == 0) ? (h->nc == 2 ? (int)gfs::ST_SU2_F32_SP : (int)gfs::ST_F32R12_SP) : st;
         gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, kst, ctd, h->W[tab]);
         if (!fn) return fail(h, GF_E_INVALID, "no kernel variant for gauge %d update %d storage %d W %d", h->gauge, upd,
                              h->storage, h->W[tab]);
@@ -774,8 +775,6 @@ int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes) {
     if (rc) return rc;
     if (h->inst.empty()) return fail(h, GF_E_STATE, "no instance added");
     if (!dev_ptr) return fail(h, GF_E_INVALID, "workspace is NULL");
-    if (h->nc == 2 && h->storage == GF_F32_R12)
-        return fail(h, GF_E_INVALID, "single-precision storage is not built for SU(2) (use mixed or FP64)");
     if (reinterpret_cast<uintptr_t>(dev_ptr) & 255) return fail(h, GF_E_NOMEM, "workspace not 256-byte aligned");
     plan_layout(h);
     if (bytes < h->need_bytes)

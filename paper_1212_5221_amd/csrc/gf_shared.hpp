@@ -11,9 +11,17 @@ enum Update { UPD_OR = 0, UPD_MICRO = 1, UPD_HEATBATH = 2, UPD_SR = 3 };
 // ST_F32R12_SP is the ST_F32R12 storage; its half-sweep kernels also apply G
 // in FP32 (single precision throughout, the F/theta sums and reprojection
 // aside).  ST_SU2_*: links of the gauge group SU(2) as their 4 Cayley-Klein
-// components.
-enum Storage { ST_F64R18 = 0, ST_F64R12 = 1, ST_F32R12 = 2, ST_F32R12_SP = 3, ST_SU2_F64 = 4, ST_SU2_F32 = 5 };
-constexpr bool is_su2(int st) { return st == ST_SU2_F64 || st == ST_SU2_F32; }
+// components; ST_SU2_F32_SP is ST_SU2_F32 with g applied in FP32.
+enum Storage {
+    ST_F64R18 = 0,
+    ST_F64R12 = 1,
+    ST_F32R12 = 2,
+    ST_F32R12_SP = 3,
+    ST_SU2_F64 = 4,
+    ST_SU2_F32 = 5,
+    ST_SU2_F32_SP = 6
+};
+constexpr bool is_su2(int st) { return st == ST_SU2_F64 || st == ST_SU2_F32 || st == ST_SU2_F32_SP; }
 
 // one lattice instance, as the kernels see it
 struct InstDev {

@@ -52,6 +52,10 @@ struct Store<gfs::ST_SU2_F32> {
     }
 };
 
+// single precision: the same storage, g applied in FP32
+template <>
+struct Store<gfs::ST_SU2_F32_SP> : Store<gfs::ST_SU2_F32> {};
+
 template <typename T, typename S>
 __device__ __forceinline__ Q4<T> q_from(const S r[4]) {
     Q4<T> q;
@@ -87,7 +91,7 @@ __device__ __forceinline__ void su2_mag_add(const Q4<T> &u, bool fwd, T &D, T &E
 // ---------------------------------------------------------------- half-sweep
 // One thread per site of the active parity (no wave split: the 8 links are
 // 32 or 64 registers).  The local g is computed in CT; on FP32 storage it is
-// normalised and applied in FP64.
+// normalised and applied in FP64 (single precision: applied in FP32).
 template <int GAUGE, int UPD, int ST, typename CT>
 __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep_su2(gfs::SweepArgs a) {
     typedef Store<ST> SD;
@@ -408,6 +412,12 @@ static sweep_fn su2_variant(int upd, int st, int ctd) {
         if (upd == gfs::UPD_MICRO) return &k_sweep_su2<G, gfs::UPD_MICRO, gfs::ST_SU2_F64, double>;
         if (upd == gfs::UPD_HEATBATH) return &k_sweep_su2<G, gfs::UPD_HEATBATH, gfs::ST_SU2_F64, double>;
         if (upd == gfs::UPD_SR) return &k_sweep_su2<G, gfs::UPD_SR, gfs::ST_SU2_F64, double>;
+        return nullptr;
+    }
+    if (st == gfs::ST_SU2_F32_SP) {
+        if (ctd) return nullptr;
+        if (upd == gfs::UPD_OR) return &k_sweep_su2<G, gfs::UPD_OR, gfs::ST_SU2_F32_SP, float>;
+        if (upd == gfs::UPD_MICRO) return &k_sweep_su2<G, gfs::UPD_MICRO, gfs::ST_SU2_F32_SP, float>;
         return nullptr;
     }
     if (st != gfs::ST_SU2_F32) return nullptr;
