@@ -1,11 +1,12 @@
-"""Plain FP64 CPU oracle for SU(3) gauge fixing (arXiv:1212.5221).
+"""Plain FP64 CPU oracle for SU(3) and SU(2) gauge fixing (arXiv:1212.5221).
 
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline
 leg of the benchmark use it to check the GPU library.  It shares no code with
 the GPU path (see ``gf_oracle.c`` for the readings of the paper it takes).
 
 Links are numpy float64 arrays in the natural layout
-(sites, 4, 3, 3, 2) = t, x, y, z, mu, i, j, re/im with z fastest.
+(sites, 4, 3, 3, 2) = t, x, y, z, mu, i, j, re/im with z fastest; the su2_*
+functions take SU(2) links (sites, 4, 2, 2, 2).
 """
 from __future__ import annotations
 

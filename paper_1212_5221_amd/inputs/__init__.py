@@ -11,6 +11,9 @@ Recipes (all keyed by a 64-bit seed, independent of thread count):
 * ``pure_gauge(dims, seed)``: U_mu(x) = h(x) h(x+mu)^dag
 * ``hot(dims, seed)``: Haar-random links
 * ``gauge_copy(U, dims, seed)``: a random gauge transform of U (Gribov copies)
+
+and, for the gauge group SU(2) (numpy, links (V, 4, 2, 2, 2)), ``su2_hot``,
+``su2_smooth``, ``su2_pure_gauge``, ``su2_gauge_field`` and ``su2_gauge_copy``.
 """
 from __future__ import annotations
 
