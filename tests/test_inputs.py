@@ -84,3 +84,49 @@ def test_generator_philox_matches_numpy():
 def test_smooth_eps_zero_is_pure_gauge():
     dims = (2, 4, 2, 2)
     np.testing.assert_allclose(I.smooth(dims, 0.0, 4), I.pure_gauge(dims, 4), atol=1e-15)
+
+
+# ---------------------------------------------------------------- SU(2)
+def _su2_cplx(U):
+    return U[..., 0] + 1j * U[..., 1]
+
+
+def test_su2_fields_are_su2_in_cayley_klein_form():
+    import numpy as np
+    from paper_1212_5221_amd import inputs as I
+    dims = (4, 4, 2, 6)
+    for U in (I.su2_hot(dims, 1), I.su2_smooth(dims, 0.4, 2), I.su2_pure_gauge(dims, 3)):
+        assert U.shape == (int(np.prod(dims)), 4, 2, 2, 2)
+        u = _su2_cplx(U)
+        eye = np.einsum("...ij,...kj->...ik", u, np.conj(u))
+        assert np.abs(eye - np.eye(2)).max() < 1e-14
+        assert np.abs(np.linalg.det(u) - 1).max() < 1e-14
+        # second row = (-conj(b), conj(a))
+        assert np.abs(u[..., 1, 0] + np.conj(u[..., 0, 1])).max() < 1e-15
+        assert np.abs(u[..., 1, 1] - np.conj(u[..., 0, 0])).max() < 1e-15
+
+
+def test_su2_hot_is_haar():
+    # Haar SU(2): <Re tr U> = 0, <|U_00|^2> = 1/2, <(Re tr U / 2)^2> = 1/4
+    import numpy as np
+    from paper_1212_5221_amd import inputs as I
+    u = _su2_cplx(I.su2_hot((8, 8, 8, 8), 4)).reshape(-1, 2, 2)
+    tr = np.trace(u, axis1=1, axis2=2).real / 2
+    n = len(tr)
+    assert abs(tr.mean()) < 5 / np.sqrt(n)
+    assert abs((np.abs(u[:, 0, 0]) ** 2).mean() - 0.5) < 5 / np.sqrt(n)
+    assert abs((tr ** 2).mean() - 0.25) < 5 / np.sqrt(n)
+
+
+def test_su2_recipes_keep_or_remove_gauge_freedom_as_stated():
+    import numpy as np
+    import oracle as O
+    from paper_1212_5221_amd import inputs as I
+    dims = (4, 4, 4, 4)
+    assert abs(O.su2_plaquette(I.su2_pure_gauge(dims, 5), dims) - 1.0) < 1e-14
+    U = I.su2_smooth(dims, 0.3, 6)
+    C = I.su2_gauge_copy(U, dims, 7)
+    assert abs(O.su2_plaquette(C, dims) - O.su2_plaquette(U, dims)) < 1e-14
+    assert np.abs(C - U).max() > 0.1
+    # deterministic per seed
+    np.testing.assert_array_equal(I.su2_smooth(dims, 0.3, 6), U)
