@@ -1,0 +1,26 @@
+"""bench.py host logic (no GPU): the one-GPU guard and the rule that measured
+HBM bytes are reported only for the kernel sources they were taken from."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_several_gpus_are_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_traffic_only_for_the_profiled_kernel_sources(monkeypatch):
+    import bench
+    digest = bench.kernel_digest()
+    assert len(digest) == 16
+    monkeypatch.setattr(bench, "COUNTER_DIGEST", digest)
+    assert bench.measured_traffic(1) == bench.COUNTER_TRAFFIC[1]
+    monkeypatch.setattr(bench, "COUNTER_DIGEST", "0" * 16)
+    assert bench.measured_traffic(1) is None
+    monkeypatch.setattr(bench, "COUNTER_DIGEST", None)
+    assert bench.measured_traffic(1) is None
