@@ -54,7 +54,13 @@
  *      link U_mu(x - mu), which transforms as U_mu(x - mu) g(x)^dag, is the
  *      forward term of U_mu(x - mu)^dag (the printed local functional leaves
  *      the second term to the reader); the heatbath weight is
- *      exp(Re tr[g K] / T) as for an SU(3) subgroup.
+ *      exp(Re tr[g K] / T) as for an SU(3) subgroup;
+ *   R13 reprojection inside a run (Sec. 4.5; the interval is the caller's):
+ *      after every reunit_every sweeps the links of every unit still running
+ *      are reprojected, and for Coulomb gauge the accumulated G(x) of those
+ *      time-slices too; a time-slice that has stopped keeps exactly the links
+ *      its stopping check measured (its links are neither updated nor
+ *      reprojected any more).
  */
 #include <complex.h>
 #include <math.h>
@@ -1010,7 +1016,9 @@ void gfo_coulomb_fix_u0(double *U, const int32_t dims[4], const double *G) {
    recorded (at most traj_cap).  sweeps_done: one entry (Landau/MAG) or Nt
    entries (Coulomb).  *sweep_counter is the global sweep index, advanced by
    the number of sweeps run (used for random streams).
-   reunit_every > 0: reproject all links after every reunit_every sweeps.
+   reunit_every > 0: after every reunit_every sweeps reproject the links of
+   the instance, or (Coulomb) the links and the accumulated transformation of
+   every time-slice still running (reading R13).
    Returns 0 if converged, 1 if some instance/slice hit max_sweeps. */
 int gfo_run(double *U, const int32_t dims[4], int32_t gauge, int32_t update, double omega, double p_sr,
             int32_t max_sweeps, double tol, int32_t check_every, int32_t reunit_every, uint64_t seed,
@@ -1064,8 +1072,20 @@ int gfo_run(double *U, const int32_t dims[4], int32_t gauge, int32_t update, dou
             for (int64_t t = 0; t < Nt; ++t)
                 if (active[t]) sweeps_done[t] = k;
             if (reunit_every > 0 && k % reunit_every == 0) {
-                gfo_reunitarise(U, 4 * g.V);
-                gfo_reunitarise(G, g.V); /* the accumulated transformation too */
+                /* R13: the four links and the accumulated transformation of
+                   every site of a time-slice still running */
+#pragma omp parallel for schedule(static)
+                for (int64_t s = 0; s < g.V; ++s) {
+                    if (!active[site_t(&g, s)]) continue;
+                    for (int mu = 0; mu < 4; ++mu) {
+                        mat3 u = link_get(U, s, mu);
+                        mat_reunitarise(&u);
+                        link_put(U, s, mu, &u);
+                    }
+                    mat3 gs = mat_get18(G + (size_t)s * 18);
+                    mat_reunitarise(&gs);
+                    mat_put18(G + (size_t)s * 18, &gs);
+                }
             }
         }
         gfo_coulomb_fix_u0(U, dims, G);

@@ -142,6 +142,28 @@ def test_reprojection_during_run_keeps_result():
     assert np.max(np.abs(U1 - U2)) < 1e-12
 
 
+def test_stopped_coulomb_slice_keeps_its_links_under_reprojection():
+    # Reading R13 (Sec. 4.5 reprojection inside a run): a time-slice whose
+    # spatial links are constant SU(3) matrices is already fixed (theta_t = 0)
+    # and stops at the first check; with reprojection every 3 sweeps its
+    # spatial links stay bit-identical, while reprojecting them would change
+    # their last bits, and the slices still running are reprojected.
+    dims = (4, 4, 4, 4)
+    vs = 64
+    U = I.smooth(dims, 0.5, 3003)
+    C = I.hot((2, 2, 2, 2), 17)[0]
+    Cr = C.copy()
+    O.reunitarise(Cr)
+    assert np.any(Cr[1:4] != C[1:4])
+    U[2 * vs:3 * vs, 1:4] = C[1:4]
+    before = U[2 * vs:3 * vs, 1:4].copy()
+    r = O.run(U, dims, "coulomb", "or", omega=1.7, max_sweeps=2000, tol=1e-12, check_every=5, reunit_every=3)
+    assert r.status == 0 and r.sweeps_done[2] == 0 and np.all(r.sweeps_done[[0, 1, 3]] > 0)
+    np.testing.assert_array_equal(U[2 * vs:3 * vs, 1:4], before)
+    mean, mx = O.unitarity(U)
+    assert mx < 1e-14
+
+
 @pytest.mark.parametrize("gauge", ["landau", "mag"])
 def test_zero_temperature_heatbath_is_relaxation(gauge):
     dims = (4, 4, 4, 4)
