@@ -91,11 +91,12 @@ def make_fixer(gf, storage):
 
 
 def one_fix(fx, inp):
-    """upload (device-resident natural layout) + fix + final FP64 reprojection; returns sweeps"""
+    """upload (device-resident natural layout) + fix; returns sweeps.  With
+    FP32 storage and reprojection in use the sweeps end with the FP64
+    reprojection of the links and a check of theta on the reprojected links
+    (more sweeps if it no longer passes)."""
     fx.upload(0, inp)
     st, done = fx.sweep("or", max_sweeps=MAX_SWEEPS, tol=TOL, check_every=CHECK)
-    if fx.storage in (2, 3):  # FP32 storages: final FP64 reprojection
-        fx.reunitarise()
     return st, int(done[0])
 
 
@@ -197,7 +198,6 @@ def workloads(gf, I):
     t_sa = time.perf_counter() - t0
     F_sa, _ = fx.measure(0)
     st, done = fx.sweep("or", max_sweeps=100000, tol=TOL, check_every=CHECK)
-    fx.reunitarise()
     torch.cuda.synchronize()
     t_all = time.perf_counter() - t0
     F, th = fx.measure(0)
@@ -223,8 +223,6 @@ def workloads(gf, I):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         umean, umax = fx.unitarity(0)
-        if storage != "f64r12":
-            fx.reunitarise()
         F, th = fx.measure(0)
         fx.close()
         study.append({"storage": storage, "reunit_every": R, "status": st, "sweeps": int(done[0]),
@@ -302,7 +300,6 @@ def workloads(gf, I):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st, done = fx.sweep("or", max_sweeps=100000, tol=TOL, check_every=CHECK)
-    fx.reunitarise()
     torch.cuda.synchronize()
     t_all = time.perf_counter() - t0
     Fs = [fx.measure(k)[0] for k in range(len(dl))]

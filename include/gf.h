@@ -130,7 +130,10 @@ int gf_set_group(gf_handle h, int nc);
    FP32 to SU(3), and rounds the result to FP32.  12-real storages store a
    left-multiplied link after one first-order renormalisation of its two rows
    (without it, rebuilding the third row lets their norm defect grow under
-   large updates).  Only before binding. */
+   large updates).  With FP32 storage (GF_MIXED_F32_R12, GF_F32_R12) and
+   reunit_every > 0, gf_sweep delivers reprojected links: a unit stops only
+   on a check of links reprojected in FP64 (see gf_sweep).  Only before
+   binding. */
 int gf_set_precision(gf_handle h, int storage, int32_t reunit_every, double fp64_tail_theta);
 
 /* Bytes of device workspace the bound configuration needs. */
@@ -180,6 +183,16 @@ int gf_set_anneal(gf_handle h, double T0, double T1, int32_t nsteps, int32_t nmi
    every `check_every` sweeps; a unit (instance; Coulomb: time-slice) stops
    at the first check with theta < theta_tol; stop when every unit stopped
    (GF_OK) or after max_sweeps sweeps (GF_NOT_CONVERGED).
+   FP32 storage with reunit_every > 0 (Sec. 4.5): once every unit has
+   stopped, the links (and the Coulomb accumulator) of every unit are
+   reprojected to SU(3) in FP64 and rounded back to FP32, and theta is
+   measured again; units whose theta is no longer below theta_tol run on in
+   chunks of check_every sweeps (within max_sweeps) until a check passes,
+   and are then reprojected and checked again.  So the delivered links are
+   reprojected and satisfy theta < theta_tol.
+   Coulomb: the U_0 fix-up follows at the end.  Stopped units are neither
+   swept nor reprojected by the periodic reprojection: a unit keeps the
+   links its stopping check measured.
    GF_ANNEAL: run the schedule of gf_set_anneal (no stopping; max_sweeps,
    theta_tol, check_every ignored).
    sweeps_done (host, may be NULL): per instance (Landau/MAG) or per

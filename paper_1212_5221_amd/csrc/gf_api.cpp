@@ -972,42 +972,98 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
         slot ^= 1;
         return GF_OK;
     };
-    int status = GF_OK;
     int k = 0;
     bool stopped = false;
+    // sweeps from k until every unit stopped (stopped = true) or max_sweeps
+    auto run_until_stopped = [&]() -> int {
+        for (;;) {
+            if (npend == 2 || (k >= max_sweeps && npend > 0)) {
+                const Pend c = pend[0];
+                pend[0] = pend[1];
+                --npend;
+                HIPCHK(h, hipEventSynchronize(h->chk_ev[c.slot]));
+                const int32_t *st = h->hstat + 4 * c.slot;
+                if (st[1] != 0) {
+                    HIPCHK(h, hipStreamSynchronize(h->stream));
+                    (void)fetch_sweeps_done(h, sweeps_done);
+                    return fail(h, GF_E_NONFINITE, "F or theta not finite in %d unit(s) after %d sweeps", st[1],
+                                c.k);
+                }
+                h->n_active = st[0];
+                h->n_tail = st[2];
+                if (st[0] == 0) {
+                    stopped = true;
+                    return GF_OK;
+                }
+                continue;
+            }
+            if (k >= max_sweeps) return GF_OK;
+            const int n = std::min(check_every - k % check_every, max_sweeps - k);
+            int r = run_sweeps(h, upd, n, k, n == check_every);
+            if (r) return r;
+            k += n;
+            if (k % check_every == 0) {
+                r = enqueue_check(k);
+                if (r) return r;
+            }
+        }
+    };
     rc = enqueue_check(0);
     if (rc) return rc;
-    for (;;) {
-        if (npend == 2 || (k >= max_sweeps && npend > 0)) {
-            const Pend c = pend[0];
-            pend[0] = pend[1];
-            --npend;
-            HIPCHK(h, hipEventSynchronize(h->chk_ev[c.slot]));
-            const int32_t *st = h->hstat + 4 * c.slot;
-            if (st[1] != 0) {
-                HIPCHK(h, hipStreamSynchronize(h->stream));
-                (void)fetch_sweeps_done(h, sweeps_done);
-                return fail(h, GF_E_NONFINITE, "F or theta not finite in %d unit(s) after %d sweeps", st[1], c.k);
+    rc = run_until_stopped();
+    if (rc) return rc;
+    // FP32 storages with reprojection in use deliver their links reprojected
+    // in FP64 (Sec. 4.5), and the reprojection rounded back to FP32 moves
+    // theta slightly: so the units that stopped are reprojected and checked
+    // again, and those whose theta is no longer below the tolerance continue
+    // (chunks of check_every sweeps, within max_sweeps) until a check on
+    // reprojected links passes.
+    const bool fp32_store = (h->storage == GF_MIXED_F32_R12 || h->storage == GF_F32_R12);
+    if (stopped && fp32_store && h->reunit_every > 0) {
+        std::vector<int32_t> ran(h->nunits, 1);  // first pass: every unit
+        for (;;) {
+            HIPCHK(h, hipStreamSynchronize(h->stream));  // queued chunks and checks have run
+            npend = 0;
+            for (int u = 0; u < h->nunits;) {
+                if (!ran[u]) {
+                    ++u;
+                    continue;
+                }
+                int v = u;
+                while (v < h->nunits && ran[v]) ++v;
+                rc = launch_reunit_units(h, false, u, v);
+                if (rc) return rc;
+                u = v;
             }
-            h->n_active = st[0];
-            h->n_tail = st[2];
-            if (st[0] == 0) {
-                stopped = true;
+            HIPCHK(h, hipMemcpyAsync(h->ws + h->off_active, ran.data(), sizeof(int32_t) * h->nunits,
+                                     hipMemcpyHostToDevice, h->stream));
+            rc = launch_measure(h, 0, true, theta_tol);
+            if (rc) return rc;
+            HIPCHK(h, hipMemcpyAsync(h->hstat, h->ws + h->off_status, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                     h->stream));
+            HIPCHK(h, hipMemcpyAsync(ran.data(), h->ws + h->off_active, sizeof(int32_t) * h->nunits,
+                                     hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            if (h->hstat[1] != 0) {
+                (void)fetch_sweeps_done(h, sweeps_done);
+                return fail(h, GF_E_NONFINITE, "F or theta not finite in %d unit(s) after reprojection", h->hstat[1]);
+            }
+            h->n_active = h->hstat[0];
+            h->n_tail = h->hstat[2];
+            if (h->n_active == 0) break;
+            if (k >= max_sweeps) {
+                stopped = false;
                 break;
             }
-            continue;
-        }
-        if (k >= max_sweeps) break;
-        const int n = std::min(check_every - k % check_every, max_sweeps - k);
-        rc = run_sweeps(h, upd, n, k, n == check_every);
-        if (rc) return rc;
-        k += n;
-        if (k % check_every == 0) {
-            rc = enqueue_check(k);
+            // k is a multiple of check_every here (a chunk ends at one, or
+            // at max_sweeps), so the chunks keep their graph patterns
+            stopped = false;
+            rc = run_until_stopped();
             if (rc) return rc;
+            if (!stopped) break;
         }
     }
-    if (!stopped) status = GF_NOT_CONVERGED;
+    int status = stopped ? GF_OK : GF_NOT_CONVERGED;
     rc = coulomb_finish(h);
     if (rc) return rc;
     rc = drain_timing(h);

