@@ -88,7 +88,8 @@ int gf_create(gf_handle *out, int hip_device, void *hip_stream);
 void gf_destroy(gf_handle h);
 
 /* Message of the last non-OK status on `h` (or of the last failed gf_create
-   when h is NULL); valid until the next call on that handle. */
+   or gf_measure_noalloc when h is NULL); valid until the next call on that
+   handle. */
 const char *gf_last_error(gf_handle h);
 
 /* Add a lattice instance of extents dims = {Nt, Nx, Ny, Nz}.  Every extent
@@ -215,6 +216,27 @@ int gf_measure(gf_handle h, int32_t inst, double *F, double *theta);
 
 /* Coulomb: per time-slice F_t, theta_t (Nt values each). */
 int gf_measure_timeslices(gf_handle h, int32_t inst, double *F_t, double *theta_t);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the F and
+   theta of gf_measure for an SU(3) field the caller holds on device
+   `hip_device`, without a handle or workspace.  links: device pointer to the
+   field in the natural layout (V*4*18 doubles, V = dims[0]*dims[1]*dims[2]*
+   dims[3]); gauge: GF_LANDAU, GF_COULOMB or GF_MAG (Coulomb: the averages
+   over the time-slices, as gf_measure); out: device pointer, receives
+   out[0] = F and out[1] = theta (no finiteness check).  Every extent even and
+   >= 2, at most GF_NOALLOC_MAX_SITES sites, else GF_E_DIMS.  The work is
+   enqueued on `hip_stream` (a stream of that device, NULL the default
+   stream) and the call returns without waiting; it allocates nothing and
+   needs no synchronisation, so it can be captured in a HIP graph.  The
+   partial sums go to a fixed array of 16 KiB in the library (2048 doubles,
+   one pair per reduction block) that each device holds for the life of the
+   process; every call on a device uses the same array, so calls that
+   overlap on one device (on different streams, or from several threads)
+   race and give wrong values.  Errors are reported by gf_last_error(NULL). */
+#define GF_NOALLOC_MAX_SITES ((int64_t)1 << 29)
+int gf_measure_noalloc(int hip_device, void *hip_stream, int gauge, const int32_t dims[4], const double *links,
+                       double *out);
 
 /* Mean and maximum of |1 - det U| over the links of `inst` (Sec. 4.5). */
 int gf_unitarity(gf_handle h, int32_t inst, double *mean, double *max);

@@ -1361,4 +1361,39 @@ int gf_set_graph(gf_handle h, int enable) {
     return GF_OK;
 }
 
+
+int gf_measure_noalloc(int hip_device, void *hip_stream, int gauge, const int32_t dims[4], const double *links,
+                       double *out) {
+    if (!dims || !links || !out) return fail(nullptr, GF_E_INVALID, "gf_measure_noalloc: dims, links or out is NULL");
+    if (gauge != GF_LANDAU && gauge != GF_COULOMB && gauge != GF_MAG)
+        return fail(nullptr, GF_E_INVALID, "gf_measure_noalloc: unknown gauge %d", gauge);
+    int64_t V = 1;
+    for (int k = 0; k < 4; ++k) {
+        if (dims[k] < 2 || (dims[k] & 1))
+            return fail(nullptr, GF_E_DIMS, "gf_measure_noalloc: extent %d of dimension %d is not even and >= 2",
+                        dims[k], k);
+        V *= dims[k];
+        if (V > GF_NOALLOC_MAX_SITES)
+            return fail(nullptr, GF_E_DIMS, "gf_measure_noalloc: lattice larger than %lld sites",
+                        (long long)GF_NOALLOC_MAX_SITES);
+    }
+    int ndev = 0, prev = -1;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return fail(nullptr, GF_E_HIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (hip_device < 0 || hip_device >= ndev)
+        return fail(nullptr, GF_E_INVALID, "gf_measure_noalloc: no HIP device %d", hip_device);
+    e = hipGetDevice(&prev);
+    if (e != hipSuccess) return fail(nullptr, GF_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (prev != hip_device) {
+        e = hipSetDevice(hip_device);
+        if (e != hipSuccess) return fail(nullptr, GF_E_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+    }
+    double *scr = nullptr;
+    e = gfl::noalloc_scratch(hip_device, &scr, nullptr);
+    if (e == hipSuccess) e = gfl::measure_nat(gauge, links, dims, out, scr, reinterpret_cast<hipStream_t>(hip_stream));
+    if (prev != hip_device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail(nullptr, GF_E_HIP, "gf_measure_noalloc: %s", hipGetErrorString(e));
+    return GF_OK;
+}
+
 }  // extern "C"

@@ -7,6 +7,9 @@
 #include "gf_launch.hpp"
 #include "gf_reduce.hpp"
 
+#include <algorithm>
+#include <mutex>
+
 namespace gfd {
 
 // traceless part of (K - K^dag)/(2i): sum |.|^2
@@ -360,6 +363,106 @@ __global__ __launch_bounds__(MBLOCK) void k_coulomb_fix(char *ws, gfs::InstDev I
     SD::store(plane_ptr<ST>(ws, I, p, 0), I.Vh, h, r);
 }
 
+
+// ---------------------------------------------------------------- no allocation
+// F and theta (Sec. 2.1) of an SU(3) field that the caller holds in the
+// natural order (18 doubles per link, z fastest, mu = 0 the time direction),
+// for callers that cannot allocate: the per-block partial sums go to the
+// fixed array `scratch` instead of a workspace.  NA_BLOCKS blocks stride
+// over the sites; block b writes partials 2b, 2b+1 on every call, so nothing
+// has to start at zero.
+constexpr int NA_BLOCKS = 1024;
+static __device__ __align__(256) double scratch[2 * NA_BLOCKS];
+
+__device__ __forceinline__ void load_nat(const double *p, M3<double> &m) {
+    const double2 *q = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double2 v = q[k];
+        m.e[k / 3][k % 3] = cmk(v.x, v.y);
+    }
+}
+
+template <int GAUGE>
+__global__ __launch_bounds__(MBLOCK) void k_measure_nat(const double *links, int32_t n0, int32_t n1, int32_t n2,
+                                                         int32_t n3, int64_t V, double *part) {
+    constexpr int MU0 = (GAUGE == gfs::COULOMB) ? 1 : 0;
+    __shared__ double sh[4];
+    const int32_t n[4] = {n0, n1, n2, n3};
+    // natural-index stride of a step in direction mu
+    const int64_t stride[4] = {(int64_t)n1 * n2 * n3, (int64_t)n2 * n3, (int64_t)n3, 1};
+    double F = 0.0, th = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * MBLOCK + threadIdx.x; i < V; i += (int64_t)gridDim.x * MBLOCK) {
+        M3<double> K;
+        m3_zero(K);  // Landau/Coulomb: K; MAG: W
+#pragma unroll
+        for (int mu = MU0; mu < 4; ++mu) {
+            M3<double> m;
+            load_nat(links + (i * 4 + mu) * 18, m);
+            if constexpr (GAUGE == gfs::MAG) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) F += cnorm2(m.e[a][a]);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) K.e[a][b] = cadd(K.e[a][b], cmulc(m.e[a][b], m.e[b][b]));
+            } else {
+                F += m.e[0][0].re + m.e[1][1].re + m.e[2][2].re;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) K.e[a][b] = cadd(K.e[a][b], m.e[a][b]);
+            }
+            // x - mu with periodic wrap
+            const int32_t c = (int32_t)((i / stride[mu]) % n[mu]);
+            const int64_t j = (c == 0) ? i + (int64_t)(n[mu] - 1) * stride[mu] : i - stride[mu];
+            load_nat(links + (j * 4 + mu) * 18, m);
+            if constexpr (GAUGE == gfs::MAG) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) K.e[a][b] = csub(K.e[a][b], cmul(cconj(m.e[a][a]), m.e[a][b]));
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) K.e[a][b] = cadd(K.e[a][b], cconj(m.e[b][a]));
+            }
+        }
+        if constexpr (GAUGE == gfs::MAG) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = a + 1; b < 3; ++b) th += cnorm2(csub(K.e[a][b], cconj(K.e[b][a])));
+        } else {
+            th += delta_norm2(K);
+        }
+    }
+    const double bF = block_sum(F, sh);
+    const double bT = block_sum(th, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = bF;
+        part[2 * blockIdx.x + 1] = bT;
+    }
+}
+
+// one block: the nb partials in a fixed order, normalised like k_finalize
+__global__ __launch_bounds__(MBLOCK) void k_measure_nat_sum(const double *part, int nb, double fnorm, double tnorm,
+                                                             double *out) {
+    __shared__ double sh[4];
+    double F = 0.0, th = 0.0;
+    for (int b = threadIdx.x; b < nb; b += MBLOCK) {
+        F += part[2 * b];
+        th += part[2 * b + 1];
+    }
+    const double bF = block_sum(F, sh);
+    const double bT = block_sum(th, sh);
+    if (threadIdx.x == 0) {
+        out[0] = bF / fnorm;
+        out[1] = bT / tnorm;
+    }
+}
+
 }  // namespace gfd
 
 // ---------------------------------------------------------------- launchers
@@ -477,6 +580,43 @@ hipError_t coulomb_fix(int st, char *ws, const gfs::InstDev &I, hipStream_t s) {
         k_coulomb_fix<gfs::ST_F64R12><<<nblk(n), MBLOCK, 0, s>>>(ws, I);
     else
         k_coulomb_fix<gfs::ST_F32R12><<<nblk(n), MBLOCK, 0, s>>>(ws, I);
+    return hipGetLastError();
+}
+
+
+// Address of this device's copy of `scratch`, looked up once per device with
+// that device current (each device holds its own copy at its own address;
+// the array's name is only a host-side stand-in).
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[64] = {};
+
+hipError_t noalloc_scratch(int dev, double **ptr, size_t *bytes) {
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    if (bytes) *bytes = sizeof(scratch);
+    return hipSuccess;
+}
+
+hipError_t measure_nat(int gauge, const double *links, const int32_t n[4], double *out, double *scr, hipStream_t s) {
+    const int64_t V = (int64_t)n[0] * n[1] * n[2] * n[3];
+    const int nb = (int)std::min<int64_t>(NA_BLOCKS, (V + MBLOCK - 1) / MBLOCK);
+    const int ndir = (gauge == gfs::COULOMB) ? 3 : 4;
+    if (gauge == gfs::LANDAU)
+        k_measure_nat<gfs::LANDAU><<<nb, MBLOCK, 0, s>>>(links, n[0], n[1], n[2], n[3], V, scr);
+    else if (gauge == gfs::COULOMB)
+        k_measure_nat<gfs::COULOMB><<<nb, MBLOCK, 0, s>>>(links, n[0], n[1], n[2], n[3], V, scr);
+    else
+        k_measure_nat<gfs::MAG><<<nb, MBLOCK, 0, s>>>(links, n[0], n[1], n[2], n[3], V, scr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_measure_nat_sum<<<1, MBLOCK, 0, s>>>(scr, nb, 3.0 * ndir * (double)V, 3.0 * (double)V, out);
     return hipGetLastError();
 }
 

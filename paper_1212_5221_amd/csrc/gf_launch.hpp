@@ -52,4 +52,11 @@ hipError_t convert_out_su2(int st, const char *ws, const gfs::InstDev &I, double
                            int reunit, hipStream_t s);
 hipError_t coulomb_fix_su2(int st, char *ws, const gfs::InstDev &I, hipStream_t s);
 
+// no-allocation measurement: the address of this device's fixed scratch
+// array (looked up on first use with device `dev` current) and its size; F
+// and theta of a natural-order FP64 SU(3) field into out[0], out[1]
+hipError_t noalloc_scratch(int dev, double **ptr, size_t *bytes);
+hipError_t measure_nat(int gauge, const double *links, const int32_t n[4], double *out, double *scratch,
+                       hipStream_t s);
+
 }  // namespace gfl

@@ -90,6 +90,7 @@ def load():
     L.gf_kernel_time.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_int64), dp]
     L.gf_set_graph.argtypes = [vp, ci]
     L.gf_set_cache_budget.argtypes = [vp, ctypes.c_int64]
+    L.gf_measure_noalloc.argtypes = [ci, vp, ci, i32p, vp, vp]
     L.gf_cache_groups.argtypes = [vp, i32p]
     _lib = L
     return L
@@ -104,6 +105,28 @@ def header_functions(path: str = HEADER):
 
 def _key(table, v):
     return table[v.lower()] if isinstance(v, str) else int(v)
+
+
+def measure_noalloc(links, dims, gauge, out, device=0, stream=None):
+    """gf_measure_noalloc: F and theta of an SU(3) field held on the device
+    (float64 CUDA tensor, natural layout) into the CUDA tensor out[0:2],
+    enqueued on `stream` (default: torch's current stream); allocates nothing
+    on the device and does not wait."""
+    import torch
+    L = load()
+    d = [int(x) for x in dims]
+    assert links.is_cuda and links.dtype == torch.float64 and links.is_contiguous()
+    assert links.numel() == int(np.prod(d)) * 4 * 18
+    assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= 2
+    if stream is None:
+        stream = torch.cuda.current_stream(int(device))
+    rc = L.gf_measure_noalloc(int(device), ctypes.c_void_p(stream.cuda_stream), _key(GAUGES, gauge),
+                              (ctypes.c_int32 * 4)(*d), ctypes.c_void_p(links.data_ptr()),
+                              ctypes.c_void_p(out.data_ptr()))
+    if rc != OK:
+        msg = L.gf_last_error(None)
+        raise GFError(rc, msg.decode() if msg else "")
+    return out
 
 
 class GaugeFixer:
