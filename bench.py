@@ -100,14 +100,46 @@ def one_fix(fx, inp):
     return st, int(done[0])
 
 
-def cpu_baseline(budget_s=12.0):
+def host_cpu():
+    """CPU model, logical CPUs this process may run on, physical cores."""
+    model, phys = None, set()
+    try:
+        cur = {}
+        for line in open("/proc/cpuinfo"):
+            if ":" not in line:
+                if "core id" in cur:
+                    phys.add((cur.get("physical id"), cur["core id"]))
+                cur = {}
+                continue
+            k, v = [x.strip() for x in line.split(":", 1)]
+            cur[k] = v
+            if k == "model name" and model is None:
+                model = v
+        if "core id" in cur:
+            phys.add((cur.get("physical id"), cur["core id"]))
+    except OSError:
+        pass
+    try:
+        logical = len(os.sched_getaffinity(0))
+    except AttributeError:
+        logical = os.cpu_count()
+    return {"model": model, "logical_cpus_available": logical, "physical_cores": len(phys) or None}
+
+
+def cpu_baseline(budget_s=12.0, one_core_sweeps=20):
     """The oracle (FP64, OpenMP over the host cores) on a bounded sample: OR
     sweeps of the seed-2001 configuration until about budget_s seconds; then
-    its rate on one core over about 6 s."""
+    its rate on one core over a window of one_core_sweeps sweeps."""
+    import ctypes
+
     import oracle as O
     from paper_1212_5221_amd import inputs as I
     U = I.smooth(DIMS, EPS, SEEDS[0])
     V = int(np.prod(DIMS))
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        gomp = None
     O.sweep(U, DIMS, "landau", "or", omega=OMEGA)  # warm-up (thread pool, pages)
     n = 0
     t0 = time.time()
@@ -117,29 +149,24 @@ def cpu_baseline(budget_s=12.0):
         if time.time() - t0 > budget_s and n >= 2:
             break
     el = time.time() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the OpenMP threads the oracle's parallel loops ran with
+    threads = gomp.omp_get_max_threads() if gomp else int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     out = {"value": V * n / el, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
-           "sample": "%d Landau OR sweeps (omega 1.7) of the 32^4 seed-2001 configuration, FP64, %.1f s" % (n, el)}
+           "sample": "%d Landau OR sweeps (omega 1.7) of the 32^4 seed-2001 configuration, FP64, %.1f s" % (n, el),
+           "host": host_cpu()}
     # the same on one core (OpenMP limited to one thread for these sweeps)
-    try:
-        import ctypes
-        gomp = ctypes.CDLL("libgomp.so.1")
+    if gomp is not None:
         before = gomp.omp_get_max_threads()
         gomp.omp_set_num_threads(1)
         try:
-            n1 = 0
             t0 = time.time()
-            while True:
+            for _ in range(one_core_sweeps):
                 O.sweep(U, DIMS, "landau", "or", omega=OMEGA)
-                n1 += 1
-                if time.time() - t0 > 6.0 and n1 >= 2:
-                    break
             el1 = time.time() - t0
         finally:
             gomp.omp_set_num_threads(before)
-        out["one_core"] = {"value": V * n1 / el1, "sample": "%d sweeps, %.1f s" % (n1, el1)}
-    except OSError:
-        pass
+        out["one_core"] = {"value": V * one_core_sweeps / el1, "cores": 1,
+                           "sample": "%d sweeps, %.1f s" % (one_core_sweeps, el1)}
     return out
 
 
@@ -190,20 +217,45 @@ def workloads(gf, I):
     fx.set_overrelax(OMEGA)
     fx.autotune(reps=5)
     fx.upload(0, inp)
+    fx.set_sweep_index(0, 0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fx.set_anneal(1.5, 0.01, 3000, nmicro=3, seed=4002)
     fx.sweep("anneal")
     torch.cuda.synchronize()
     t_sa = time.perf_counter() - t0
-    F_sa, _ = fx.measure(0)
+    F_sa, th_sa = fx.measure(0)
+    st, done = fx.sweep("or", max_sweeps=100000, tol=TOL, check_every=CHECK)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    F, th = fx.measure(0)
+    print(json.dumps({"workload": "mag-32^4-eps0.7-anneal3000-T1.5to0.01-then-or", "anneal_s": round(t_sa, 3),
+                      "anneal_sweeps": 12000, "F_after_anneal": F_sa, "or_sweeps": int(done[0]), "status": st,
+                      "total_s": round(t_all, 3), "F": F, "theta": th}), flush=True)
+    # the cooling pipeline of the annealing study: the same annealing, then
+    # stochastic relaxation (p = 0.5) for at most 2000 sweeps until theta <
+    # 1e-8, then overrelaxation to theta < 1e-12 (same random streams)
+    fx.upload(0, inp)
+    fx.set_sweep_index(0, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fx.sweep("anneal")
+    torch.cuda.synchronize()
+    t_sa = time.perf_counter() - t0
+    fx.set_stochastic(0.5)
+    st_sr, d_sr = fx.sweep("sr", max_sweeps=2000, tol=1e-8, check_every=CHECK)
+    torch.cuda.synchronize()
+    t_sr = time.perf_counter() - t0
+    F_sr, th_sr = fx.measure(0)
     st, done = fx.sweep("or", max_sweeps=100000, tol=TOL, check_every=CHECK)
     torch.cuda.synchronize()
     t_all = time.perf_counter() - t0
     F, th = fx.measure(0)
     fx.close()
-    print(json.dumps({"workload": "mag-32^4-eps0.7-anneal3000-T1.5to0.01-then-or", "anneal_s": round(t_sa, 3),
-                      "anneal_sweeps": 12000, "F_after_anneal": F_sa, "or_sweeps": int(done[0]), "status": st,
+    print(json.dumps({"workload": "mag-32^4-eps0.7-anneal3000-then-sr-then-or", "anneal_s": round(t_sa, 3),
+                      "F_after_anneal": F_sa, "theta_after_anneal": th_sa, "sr_sweeps": int(d_sr[0]),
+                      "sr_status": st_sr, "sr_s": round(t_sr - t_sa, 3), "F_after_sr": F_sr,
+                      "theta_after_sr": th_sr, "or_sweeps": int(done[0]), "status": st,
                       "total_s": round(t_all, 3), "F": F, "theta": th}), flush=True)
 
     # precision study (Sec. 4.5): the 32^4 Landau fix of seed 2001 in single
@@ -310,6 +362,9 @@ def workloads(gf, I):
     print(json.dumps({"workload": "landau-gribov-batch-32-copies", "status": st, "total_s": round(t_all, 3),
                       "site_updates_per_s": su / t_all, "sweeps": done.tolist(), "cache_groups": groups,
                       "best_F": best}), flush=True)
+    gribov_annealing(gf, torch, shapes, ncopy, dl, ins)
+    del ins
+    landau_temperature_scan(gf, torch, I)
 
     # gauge group SU(2): 32^4 Landau and MAG fixes (overrelaxation to
     # theta < 1e-12) in mixed and FP64 storage; the second of two runs is timed
@@ -356,6 +411,81 @@ def workloads(gf, I):
     print(json.dumps({"workload": "su2-mag-32^4-hot-anneal1000-T1.5to0.01-then-or", "anneal_s": round(t_sa, 4),
                       "F_after_anneal": F_sa, "or_status": st, "or_sweeps": int(done[0]),
                       "total_s": round(t_all, 4), "F": F, "theta": th, "unitarity_max": x}), flush=True)
+
+
+def gribov_annealing(gf, torch, shapes, ncopy, dl, ins, nsteps=3000, T0=4.0, T1=1e-4, tol=1e-10):
+    """Global-maximum search over Gribov copies (Landau gauge): the 32 copies
+    of the batch fixed by overrelaxation alone (0 annealing steps) and after
+    simulated annealing (nsteps steps, T linear from T0 to T1, heatbath + 3
+    microcanonical sweeps each, Philox key 7001), both to theta < tol, in one
+    batched launch each.  Per copy F_rel = (F_max - F) / F_max with F_max the
+    largest F found for its lattice by either run."""
+    res = {}
+    for steps in (0, nsteps):
+        fx = gf.GaugeFixer(dl, gauge="landau", storage="mixed", reunit_every=100, tail_theta=1e-9)
+        for k, x in enumerate(ins):
+            fx.upload(k, x)
+        fx.set_overrelax(OMEGA)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if steps:
+            fx.set_anneal(T0, T1, steps, nmicro=3, seed=7001)
+            fx.sweep("anneal")
+        torch.cuda.synchronize()
+        t_sa = time.perf_counter() - t0
+        st, done = fx.sweep("or", max_sweeps=100000, tol=tol, check_every=CHECK)
+        torch.cuda.synchronize()
+        t_all = time.perf_counter() - t0
+        Fs = [fx.measure(k)[0] for k in range(len(dl))]
+        fx.close()
+        res[steps] = {"F": Fs, "or_sweeps": done.tolist(), "status": st, "anneal_s": round(t_sa, 3),
+                      "total_s": round(t_all, 3)}
+    out = {"workload": "landau-gribov-batch-32-copies-annealing-search", "anneal_steps": nsteps,
+           "T0": T0, "T1": T1, "tol": tol, "lattices": {}}
+    for i, d in enumerate(shapes):
+        sl = slice(i * ncopy, (i + 1) * ncopy)
+        Fmax = max(max(res[s]["F"][sl]) for s in res)
+        out["lattices"]["x".join(map(str, d))] = {
+            "F_max": Fmax,
+            **{"steps_%d" % s: {"best_F": max(res[s]["F"][sl]),
+                                 "F_rel": [float("%.3e" % ((Fmax - f) / Fmax)) for f in res[s]["F"][sl]],
+                                 "or_sweeps": res[s]["or_sweeps"][sl]} for s in res}}
+    for s in res:
+        out["steps_%d" % s] = {k: res[s][k] for k in ("status", "anneal_s", "total_s")}
+    print(json.dumps(out), flush=True)
+
+
+def landau_temperature_scan(gf, torch, I, nsteps=3000, T0=4.0, T1=1e-4, nseg=10):
+    """Landau gauge on a hot (Haar-random) 32^4 field: simulated annealing
+    over nsteps steps (T linear from T0 to T1, heatbath + 3 microcanonical
+    sweeps each), run as nseg consecutive pieces of the same schedule with F
+    and theta measured after each, then overrelaxation to theta < 1e-12."""
+    dims = (32, 32, 32, 32)
+    hot = torch.from_numpy(I.hot(dims, 6101).reshape(-1)).to("cuda:0")
+    fx = gf.GaugeFixer([dims], gauge="landau", storage="mixed", reunit_every=100, tail_theta=1e-9)
+    fx.upload(0, hot)
+    fx.set_overrelax(OMEGA)
+    Ts = [T0 + (T1 - T0) * k / (nsteps - 1) for k in range(nsteps)]
+    F, th = fx.measure(0)
+    scan = [{"step": 0, "T": T0, "F": F, "theta": th}]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    edges = [round(nsteps * j / nseg) for j in range(nseg + 1)]
+    for a, b in zip(edges[:-1], edges[1:]):
+        fx.set_anneal(Ts[a], Ts[b - 1], b - a, nmicro=3, seed=6102)
+        fx.sweep("anneal")
+        F, th = fx.measure(0)
+        scan.append({"step": b, "T": Ts[b - 1], "F": F, "theta": th})
+    torch.cuda.synchronize()
+    t_sa = time.perf_counter() - t0
+    st, done = fx.sweep("or", max_sweeps=100000, tol=TOL, check_every=CHECK)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    F, th = fx.measure(0)
+    fx.close()
+    print(json.dumps({"workload": "landau-32^4-hot-anneal-temperature-scan", "scan": scan, "anneal_s": round(t_sa, 3),
+                      "or_sweeps": int(done[0]), "status": st, "F": F, "theta": th,
+                      "total_s": round(t_all, 3)}), flush=True)
 
 
 def kernel_table(gf, I, nsweeps=20):

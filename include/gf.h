@@ -305,6 +305,22 @@ int gf_cache_groups(gf_handle h, int32_t *groups);
    the reprojection interval) and replayed. */
 int gf_set_graph(gf_handle h, int enable);
 
+/* Streaming ceiling (measurement only, no part of the method): the plain
+   memory traffic one half-sweep is compared with.  kind GF_STREAM_COPY*:
+   copy `bytes` from `src` to `dst` (device pointers, 16-byte aligned, bytes
+   a multiple of 16), 16-byte loads and stores, optionally non-temporal;
+   GF_STREAM_READ: read `bytes` of `src` and write one float per 4 KiB block
+   to `dst` (gf_stream_blocks gives the count; dst must hold that many).
+   Enqueued on `hip_stream`; returns without waiting.  GF_E_INVALID for bad
+   arguments, GF_E_HIP if the launch fails. */
+#define GF_STREAM_COPY 0
+#define GF_STREAM_COPY_NT_LOAD 1
+#define GF_STREAM_COPY_NT_STORE 2
+#define GF_STREAM_COPY_NT 3
+#define GF_STREAM_READ 4
+int gf_stream(void *hip_stream, int kind, void *dst, const void *src, size_t bytes);
+int gf_stream_blocks(size_t bytes, int64_t *blocks);
+
 #ifdef __cplusplus
 }
 #endif

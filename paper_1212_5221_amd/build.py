@@ -24,7 +24,7 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I" + os.path.join(os.path.dirname(HERE), "include")]
 
 SOURCES = ["gf_api.cpp", "gf_kernels.hip", "gf_sweep_landau.hip", "gf_sweep_coulomb.hip", "gf_sweep_mag.hip",
-           "gf_sweep_su2.hip"]
+           "gf_sweep_su2.hip", "gf_stream.hip"]
 
 
 def _compile(src: str) -> str:

@@ -91,6 +91,8 @@ def load():
     L.gf_set_graph.argtypes = [vp, ci]
     L.gf_set_cache_budget.argtypes = [vp, ctypes.c_int64]
     L.gf_measure_noalloc.argtypes = [ci, vp, ci, i32p, vp, vp]
+    L.gf_stream.argtypes = [vp, ci, vp, vp, ctypes.c_size_t]
+    L.gf_stream_blocks.argtypes = [ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64)]
     L.gf_cache_groups.argtypes = [vp, i32p]
     _lib = L
     return L
@@ -127,6 +129,29 @@ def measure_noalloc(links, dims, gauge, out, device=0, stream=None):
         msg = L.gf_last_error(None)
         raise GFError(rc, msg.decode() if msg else "")
     return out
+
+
+STREAM_KINDS = {"copy": 0, "copy_nt_load": 1, "copy_nt_store": 2, "copy_nt": 3, "read": 4}
+
+
+def stream(kind, dst, src, nbytes, stream=None):
+    """gf_stream: one streaming pass (copy or read) over nbytes of CUDA
+    tensors, enqueued on `stream` (default: torch's current stream)."""
+    import torch
+    L = load()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    rc = L.gf_stream(ctypes.c_void_p(stream.cuda_stream), STREAM_KINDS[kind], ctypes.c_void_p(dst.data_ptr()),
+                     ctypes.c_void_p(src.data_ptr()), int(nbytes))
+    if rc != OK:
+        raise GFError(rc, "gf_stream failed")
+
+
+def stream_blocks(nbytes):
+    n = ctypes.c_int64()
+    if load().gf_stream_blocks(int(nbytes), ctypes.byref(n)) != OK:
+        raise GFError(E_INVALID, "gf_stream_blocks: bytes must be a multiple of 16")
+    return n.value
 
 
 class GaugeFixer:

@@ -128,6 +128,53 @@ def test_cooling_pipeline_matches_oracle(gauge):
     assert np.max(np.abs(out - ref)) < 1e-8
 
 
+def test_batched_gribov_annealing_matches_oracle():
+    # the annealing search over Gribov copies (Landau gauge, FP64): random
+    # gauge copies of two uneven lattices in one batch, two annealing steps
+    # (T 4 then 1e-4, 3 microcanonical sweeps each; each copy has its own
+    # Philox key (seed, instance)), then overrelaxation to theta < 1e-10 per
+    # copy.  The oracle runs each copy alone with the same key: links after
+    # the annealing to 1e-7 (two steps amplify rounding by about 1e6), then
+    # identical overrelaxation sweep counts and F to 1e-12; and the ranking
+    # of the copies by F, which is what the search reports, is the same.
+    shapes = [(4, 4, 6, 4), (6, 4, 4, 2)]
+    ncopy = 3
+    dl = [d for d in shapes for _ in range(ncopy)]
+    say("batched gribov annealing", dl)
+    Us = []
+    for li, d in enumerate(shapes):
+        base = I.smooth(d, 0.5, 7101 + li)
+        for c in range(ncopy):
+            Us.append(I.gauge_copy(base.copy(), d, 7200 + 8 * li + c))
+    fx = fixer(dl, "landau", "f64r18")
+    for k, U in enumerate(Us):
+        fx.upload(k, U)
+    fx.set_anneal(4.0, 1e-4, 2, nmicro=3, seed=7001)
+    fx.sweep("anneal")
+    mids = [fx.download(k) for k in range(len(dl))]
+    fx.set_overrelax(1.7)
+    st, done = fx.sweep("or", max_sweeps=5000, tol=1e-10, check_every=5)
+    Fg = [fx.measure(k)[0] for k in range(len(dl))]
+    fx.close()
+    assert st == 0
+    Fo = []
+    for k, (U, d) in enumerate(zip(Us, dl)):
+        ref = U.copy()
+        ctr = O.anneal(ref, d, "landau", 4.0, 1e-4, 2, nmicro=3, seed=7001, instance=k, sweep_counter=0)
+        assert ctr == 8
+        err = np.max(np.abs(mids[k] - ref))
+        r = O.run(ref, d, "landau", "or", omega=1.7, max_sweeps=5000, tol=1e-10, check_every=5, sweep_counter=ctr)
+        Fo.append(O.measure(ref, d, "landau")[0])
+        say("copy", k, "annealed |gpu - oracle|", err, "OR sweeps", int(done[k]), int(r.sweeps_done[0]),
+            "F", Fg[k], Fo[k])
+        assert err < 1e-7
+        assert r.status == 0 and int(done[k]) == int(r.sweeps_done[0])
+        assert abs(Fg[k] - Fo[k]) < 1e-12
+    for li in range(len(shapes)):
+        sl = slice(li * ncopy, (li + 1) * ncopy)
+        assert int(np.argmax(Fg[sl])) == int(np.argmax(Fo[sl]))
+
+
 def test_anneal_resume_is_bit_identical():
     # checkpoint/resume: the random streams depend only on (seed, instance,
     # sweep index, site), so two halves with the sweep index carried over

@@ -177,6 +177,31 @@ def test_c1_landau_trajectory(storage):
     assert np.all(dth <= bound)
 
 
+@pytest.mark.parametrize("storage", ["f64r18", "f64r12"])
+@pytest.mark.parametrize("gauge", ["landau", "coulomb", "mag"])
+def test_c1_pure_gauge_8x4(gauge, storage):
+    # 8^4 pure gauge h(x) h(x + mu)^dag (seed 1002), omega = 1.7, theta <
+    # 1e-14 checked after every sweep: the same sweep counts as the oracle
+    # (per time-slice for Coulomb), F = 1 and the links equal to the oracle's
+    dims = (8, 8, 8, 8)
+    say("C1 pure gauge", gauge, storage)
+    U = I.pure_gauge(dims, 1002)
+    ref = U.copy()
+    r = O.run(ref, dims, gauge, "or", omega=1.7, max_sweeps=2000, tol=1e-14, check_every=1)
+    fx = fixer([dims], gauge, storage)
+    fx.upload(0, U)
+    fx.set_overrelax(1.7)
+    st, done = fx.sweep("or", max_sweeps=2000, tol=1e-14, check_every=1)
+    F, th = fx.measure(0)
+    out = fx.download(0)
+    fx.close()
+    say("oracle sweeps", r.sweeps_done.tolist()[:4], "gpu", done.tolist()[:4], "F - 1 =", F - 1, "theta", th)
+    assert st == 0 and r.status == 0
+    np.testing.assert_array_equal(done, r.sweeps_done.astype(np.int32))
+    assert abs(F - 1) < 1e-12 and th < 1e-14
+    assert np.max(np.abs(out - ref)) < 1e-9
+
+
 @pytest.mark.parametrize("gauge", ["landau", "coulomb", "mag"])
 def test_full_run_matches_oracle(gauge):
     dims = (4, 6, 4, 6)
