@@ -44,17 +44,20 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"mixed": 768, "f64r12": 1536, "f64r18": 2304}  # 8 links loaded + stored
 
 
-# HBM bytes per launch of the FP32-update half-sweep (by waves per site
-# group), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes over this workload,
-# each scaled by what the counter reads for a plain 1 GiB device copy
-# (profiles/k_sweep_landau_32x4_mixed_hbm_bytes.md).  They hold for the
-# kernel sources with the digest below; after any change of those sources
-# the traffic is reported as null until the counters are taken again.
+# Bytes per launch of the FP32-update half-sweep between L2 and the fabric
+# (by launch shape "W/B/flags"), from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# passes over this workload, each scaled by what the counter reads for a
+# plain 1 GiB device copy (profiles/k_sweep_landau_32x4_mixed_hbm_bytes.md).
+# These counters count L2 misses sent to the memory side, Infinity-Cache
+# hits included.  They hold for the kernel sources with the digest below;
+# after any change of those sources the traffic is reported as null until
+# the counters are taken again.
 COUNTER_SOURCES = ("paper_1212_5221_amd/csrc/gf_sweep.hpp", "paper_1212_5221_amd/csrc/gf_device.hpp",
-                   "paper_1212_5221_amd/csrc/gf_shared.hpp", "paper_1212_5221_amd/csrc/gf_sweep_landau.hip",
+                   "paper_1212_5221_amd/csrc/gf_shared.hpp", "paper_1212_5221_amd/csrc/gf_variants.hpp",
+                   "paper_1212_5221_amd/csrc/gf_sweep_table.hpp", "paper_1212_5221_amd/csrc/gf_sweep_inst.hip",
                    "paper_1212_5221_amd/build.py")
-COUNTER_DIGEST = "df96ddbb5cf1a0ce"
-COUNTER_TRAFFIC = {1: 402902697, 2: 402935656, 4: 402951422}
+COUNTER_DIGEST = None
+COUNTER_TRAFFIC = {}
 
 
 def kernel_digest():
@@ -66,10 +69,10 @@ def kernel_digest():
     return d.hexdigest()[:16]
 
 
-def measured_traffic(waves):
+def measured_traffic(shape_key):
     if COUNTER_DIGEST is None or kernel_digest() != COUNTER_DIGEST:
         return None
-    return COUNTER_TRAFFIC.get(waves)
+    return COUNTER_TRAFFIC.get(shape_key)
 
 
 def fp64_policy():
@@ -170,26 +173,68 @@ def cpu_baseline(budget_s=12.0, one_core_sweeps=20):
     return out
 
 
-def copy_ceiling(torch, nbytes, reps=20):
-    """A plain device-to-device copy that reads and writes nbytes (the bytes
-    one half-sweep reads and writes), median of reps timed copies: a measured
-    bandwidth ceiling beside the 8 TB/s peak."""
-    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+def copy_ceiling(gf, torch, nbytes, reps=20):
+    """The streaming kernels of the library (gf_stream: 16-byte loads and
+    stores) reading and writing nbytes each (the bytes one half-sweep reads
+    and writes), cached and with non-temporal loads and stores, and reading
+    only; median of reps back-to-back passes each, as GB/s of bytes moved."""
+    nbytes = nbytes // 16 * 16
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
     y = torch.empty_like(x)
-    for _ in range(3):
-        y.copy_(x)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    ts = []
-    for _ in range(reps):
-        e0.record()
-        y.copy_(x)
-        e1.record()
-        e1.synchronize()
-        ts.append(e0.elapsed_time(e1))
-    ms = float(np.median(ts))
-    del x, y
-    return {"bytes": 2 * nbytes, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9, "kernel": "device copy (hipMemcpyAsync)"}
+    sink = torch.empty(gf.stream_blocks(nbytes), dtype=torch.float32, device="cuda:0")
+    out = {"bytes_read": nbytes, "kernel": "gf_stream (16-byte loads and stores)"}
+    for kind in ("copy", "copy_nt", "read"):
+        dst, moved = (sink, nbytes) if kind == "read" else (y, 2 * nbytes)
+        for _ in range(3):
+            gf.stream(kind, dst, x, nbytes)
+        ts = []
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        for _ in range(reps):
+            e0.record()
+            gf.stream(kind, dst, x, nbytes)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        out[kind + "_GBs"] = moved / (float(np.median(ts)) * 1e-3) / 1e9
+    del x, y, sink
+    torch.cuda.empty_cache()
+    return out
+
+
+def beyond_cache(gf, torch, I, L=48, sweeps=40):
+    """The same half-sweep on an L^4 lattice (L = 48: 1.02 GB of FP32-12
+    links, four times the 256 MB Infinity Cache), smooth input (eps 0.5,
+    seed 2001) generated and uploaded in slabs of 8 time-slices, autotuned:
+    the mean launch time of the FP32-update half-sweep over `sweeps` OR
+    sweeps (kernel events on the launch stream), against the 8 TB/s peak and
+    the streaming kernels over the same bytes."""
+    dims = (L, L, L, L)
+    V = L ** 4
+    fx = gf.GaugeFixer([dims], gauge="landau", storage="mixed", reunit_every=REUNIT)
+    for t0 in range(0, L, 8):
+        slab = torch.from_numpy(I.smooth(dims, EPS, SEEDS[0], t0=t0, nt=8).reshape(-1)).to("cuda:0")
+        fx.upload(0, slab, t0=t0, nt=8)
+        del slab
+    fx.set_overrelax(OMEGA)
+    fx.autotune(reps=3)
+    shape = fx.get_shape("fp32")
+    fx.set_timing(True)
+    fx.sweep("or", max_sweeps=sweeps, tol=0.0, check_every=CHECK)
+    n, ms = fx.kernel_time("fp32")
+    fx.set_timing(False)
+    fx.close()
+    bpl = BYTES_PER_SITE["mixed"] * V / 2
+    achieved = bpl / (ms * 1e-3) / 1e9
+    torch.cuda.empty_cache()
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "lattice": list(dims),
+            "link_bytes": 48 * 4 * V, "kernel": "k_sweep (half-sweep)",
+            "shape": {"waves_per_site_group": shape[0], "block": shape[1],
+                      "nontemporal": bool(shape[2] & gf.SHAPE_NONTEMPORAL),
+                      "xcd_tiles": not (shape[2] & gf.SHAPE_LINEAR_TILES)},
+            "bytes_per_launch": bpl, "mean_launch_ms": ms, "launches": n,
+            "copy_ceiling": copy_ceiling(gf, torch, int(bpl) // 2)}
 
 
 def workloads(gf, I):
@@ -306,8 +351,9 @@ def workloads(gf, I):
         ms = (time.perf_counter() - t0) / (2 * CHECK) * 1e3
         out["groups_%d" % fx.cache_groups()] = {"ms_per_sweep": round(ms, 3),
                                                  "GBs": round(672 * 256 * vs / (ms * 1e-3) / 1e9)}
-    fx.close()
     print(json.dumps(out), flush=True)
+    coulomb_stop_distribution(fx, torch, I, dims)
+    fx.close()
 
     # MAG on a hot (Haar-random) 16^4 configuration: annealing from several
     # starting temperatures to T = 0.01 (1000 steps, 3 microcanonical sweeps
@@ -411,6 +457,33 @@ def workloads(gf, I):
     print(json.dumps({"workload": "su2-mag-32^4-hot-anneal1000-T1.5to0.01-then-or", "anneal_s": round(t_sa, 4),
                       "F_after_anneal": F_sa, "or_status": st, "or_sweeps": int(done[0]),
                       "total_s": round(t_all, 4), "F": F, "theta": th, "unitarity_max": x}), flush=True)
+
+
+def coulomb_stop_distribution(fx, torch, I, dims, max_sweeps=10000, slab=16):
+    """The 64^3 x 256 Coulomb input (eps 0.5, seed 3001, generated and
+    uploaded in slabs of 16 time-slices) fixed by overrelaxation with
+    per-time-slice stopping at theta_t < 1e-12, bounded at max_sweeps
+    sweeps: how many time-slices stopped, the distribution of their sweep
+    counts, and theta_t of those still running."""
+    for t0 in range(0, dims[0], slab):
+        x = torch.from_numpy(I.smooth(dims, 0.5, 3001, t0=t0, nt=slab).reshape(-1)).to("cuda:0")
+        fx.upload(0, x, t0=t0, nt=slab)
+        del x
+    fx.set_cache_budget(224 << 20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, done = fx.sweep("or", max_sweeps=max_sweeps, tol=TOL, check_every=CHECK)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    F_t, th_t = fx.measure_timeslices(0)
+    stopped = done < max_sweeps
+    q = np.percentile(done[stopped], [0, 25, 50, 75, 100]).tolist() if stopped.any() else []
+    print(json.dumps({"workload": "coulomb-64^3x256-stop-distribution", "max_sweeps": max_sweeps, "status": st,
+                      "s": round(el, 2), "stopped": int(stopped.sum()), "of": int(dims[0]),
+                      "stop_sweeps_quartiles": q,
+                      "theta_t_max_running": float(th_t[~stopped].max()) if (~stopped).any() else None,
+                      "theta_t_max_stopped": float(th_t[stopped].max()) if stopped.any() else None,
+                      "F_t_min": float(F_t.min()), "F_t_max": float(F_t.max())}), flush=True)
 
 
 def gribov_annealing(gf, torch, shapes, ncopy, dl, ins, nsteps=3000, T0=4.0, T1=1e-4, tol=1e-10):
@@ -572,6 +645,9 @@ def main():
                     help="only time the half-sweep of every gauge, storage and update on 32^4 (one JSON line each)")
     ap.add_argument("--profile-sweeps", type=int, default=0,
                     help="only run this many OR sweeps of the workload (for profiler counter runs)")
+    ap.add_argument("--profile-heatbath", type=int, default=0,
+                    help="only run this many heatbath sweeps (T = 0.5) of the 32^4 workload in Landau and MAG gauge, "
+                         "mixed storage (for profiler counter runs)")
     ap.add_argument("--profile-su2", type=int, default=0,
                     help="only run this many OR sweeps of the 32^4 SU(2) Landau field, mixed storage "
                          "(for profiler counter runs)")
@@ -600,6 +676,23 @@ def main():
         return
     if args.workloads:
         workloads(gf, I)
+        return
+    if args.profile_heatbath:
+        # heatbath half-sweeps of seed 2001 at a fixed temperature, default
+        # launch shapes, kernel time from events on the launch stream
+        U = I.smooth(DIMS, EPS, SEEDS[0])
+        out = {"profile_heatbath_sweeps": args.profile_heatbath, "T": 0.5}
+        for gauge in ("landau", "mag"):
+            fx = gf.GaugeFixer([DIMS], gauge=gauge, storage="mixed", reunit_every=0)
+            fx.upload(0, U)
+            fx.set_temperature(0.5)
+            fx.set_seed(7)
+            fx.set_timing(True)
+            fx.sweep("heatbath", max_sweeps=args.profile_heatbath, tol=0.0, check_every=args.profile_heatbath)
+            n, ms = fx.kernel_time("all")
+            out[gauge] = {"launches": n, "mean_launch_ms": ms, "shape": fx.get_shape("heatbath")}
+            fx.close()
+        print(json.dumps(out), flush=True)
         return
     if args.profile_su2:
         # 32^4 SU(2), eps 0.5, seed 2001: one upload, then the sweeps in one
@@ -643,7 +736,9 @@ def main():
     fx = make_fixer(gf, "mixed")
     fx.upload(0, inputs[0])  # autotune on the workload's data (it runs real sweeps)
     lanes, _ = fx.autotune(reps=10)
-    log("autotune: waves per site group", lanes)
+    shape = fx.get_shape("fp32")
+    shape_key = "%d/%d/%d" % shape
+    log("autotune: waves per site group, block, flags", shape)
     for w in range(args.warmup):
         one_fix(fx, inputs[w % len(SEEDS)])
     torch.cuda.synchronize()
@@ -705,7 +800,8 @@ def main():
         ttt["fp64_sweeps"] = sw
         ttt["speedup_mixed_vs_fp64"] = round(sum(tt) / sum(per_step[:len(tt)]), 3)
 
-    ceiling = copy_ceiling(torch, int(bytes_per_launch) // 2)
+    ceiling = copy_ceiling(gf, torch, int(bytes_per_launch) // 2)
+    big = beyond_cache(gf, torch, I)
     # the same input handed over from host memory (pageable numpy array):
     # the PCIe-inclusive cost of a fix, reported beside the HBM-resident value
     host_in = I.smooth(DIMS, EPS, SEEDS[0])
@@ -734,18 +830,24 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "landau-32^4-eps0.5-seeds2001-2004-omega1.7-theta1e-12", "lattice": list(DIMS),
-                   "gauge": "landau", "storage": "fp32-12real", "fp64": fp64_policy(), "check_every": CHECK, "waves_per_site_group": lanes,
+                   "gauge": "landau", "storage": "fp32-12real", "fp64": fp64_policy(), "check_every": CHECK,
+                   "launch_shape": {"waves_per_site_group": shape[0], "block": shape[1],
+                                    "nontemporal": bool(shape[2] & gf.SHAPE_NONTEMPORAL),
+                                    "xcd_tiles": not (shape[2] & gf.SHAPE_LINEAR_TILES)},
                    "status": status, "sweeps": sweeps},
         "hbm_gbs_effective": eff_gbs,
         "time_to_theta": ttt,
         "host_upload_ms": host_upload_ms,
         "F_vs_oracle": F_err,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(lanes),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(shape_key),
                      "kernel": "k_sweep (half-sweep)", "bytes_per_launch": bytes_per_launch,
                      "mean_launch_ms": mean_ms, "launches": launches, "timed_chunks_every": TIME_EVERY,
                      "fp64_tail_launches": launches64, "fp64_tail_mean_ms": mean_ms64,
-                     "copy_ceiling": ceiling},
+                     "copy_ceiling": ceiling,
+                     "note": "the 201 MB of links stay partly in the 256 MB Infinity Cache between half-sweeps; "
+                             "traffic counts L2-to-fabric bytes (FETCH_SIZE, WRITE_SIZE), cache hits included"},
+        "roofline_beyond_cache": big,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

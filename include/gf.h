@@ -250,26 +250,65 @@ int gf_reunitarise(gf_handle h);
 int gf_get_sweep_index(gf_handle h, int32_t inst, uint64_t *index);
 int gf_set_sweep_index(gf_handle h, int32_t inst, uint64_t index);
 
-/* Kernel configuration.  waves_per_site: wavefronts sharing a group of 64
-   sites, each holding 8/waves_per_site (Coulomb 6/waves_per_site) of the
-   adjacent links, with the partial sums exchanged through LDS (the
-   eight-threads-per-site idea of Sec. 4.3 at wavefront granularity): 1, 2 or
-   4 (Coulomb 1 or 2); 0 = library default (FP32 update 1, FP64 update 4
-   where available; heatbath 1 on FP32 storage, 2 on FP64-12, 4 on FP64-18).
-   Applies to the FP32-update, the FP64-update and the heatbath kernels where
-   the variant exists.  block: threads per workgroup, 256 (or 0).
-   GF_E_INVALID for an unavailable variant. */
+/* Kernel configuration (launch shapes).  The half-sweep kernels come in
+   three tables: GF_KERNELS_FP32 (update computed in FP32: mixed and single
+   storage), GF_KERNELS_FP64 (update in FP64: FP64 storage, the FP64 tail of
+   mixed storage, stochastic relaxation) and GF_KERNELS_HEATBATH (heatbath
+   and annealing).  A shape is:
+   - waves_per_site: wavefronts sharing a group of 64 sites, each holding
+     8/waves_per_site (Coulomb 6/waves_per_site) of the adjacent links, with
+     the partial sums exchanged through LDS (the eight-threads-per-site idea
+     of Sec. 4.3 at wavefront granularity): 1, 2 or 4 (Coulomb 1 or 2; SU(2)
+     1);
+   - block: threads per workgroup, 64, 128, 256 or 512, at least
+     64*waves_per_site (a block updates block/waves_per_site sites);
+   - flags: GF_SHAPE_NONTEMPORAL loads and stores the links with the
+     non-temporal (streaming) cache policy (overrelaxation and
+     microcanonical kernels; SU(3) only), GF_SHAPE_LINEAR_TILES hands tile b
+     to block b instead of giving every XCD a contiguous range of tiles.
+   The default is waves_per_site 1 for the FP32 update, 4 (or the largest
+   available) for the FP64 update, for the heatbath 1 on FP32 storage, 2 on
+   FP64-12, 4 on FP64-18; block 256; no flags.  Results do not depend on the
+   shape beyond rounding.
+   gf_set_launch sets waves_per_site and block (0 = default) on every table
+   that has such a variant, without flags (GF_E_INVALID if none has);
+   gf_set_shape sets one table (GF_E_INVALID for a variant that is not
+   built); gf_get_shape reads one. */
+#define GF_KERNELS_FP32 0
+#define GF_KERNELS_FP64 1
+#define GF_KERNELS_HEATBATH 2
+#define GF_SHAPE_NONTEMPORAL 1
+#define GF_SHAPE_LINEAR_TILES 2
 int gf_set_launch(gf_handle h, int waves_per_site, int block);
+int gf_set_shape(gf_handle h, int kernels, int waves_per_site, int block, int flags);
+int gf_get_shape(gf_handle h, int kernels, int *waves_per_site, int *block, int *flags);
 
-/* Time the available variants of the OR half-sweep on the bound
-   configuration, separately for each compute precision the configuration
-   uses, and keep the one with the smallest median sweep time.  `reps`
-   rounds visit every variant in turn; a visit runs one untimed OR sweep and
-   then times 3 back-to-back OR sweeps with two events (real sweeps: they
-   advance the fixing, 4 reps sweeps per variant).  *waves_per_site (of the
-   precision doing most sweeps) and *block (may be NULL) receive the
-   choice. */
+/* Autotuning (Sec. 4.3, 4.4: the paper picks threads per site and block
+   size by measurement).  gf_autotune times every shape of the tables the
+   OR sweeps of the bound configuration use (FP32 and/or FP64 update) and
+   keeps the fastest; gf_autotune_heatbath does the same for the heatbath
+   table at the temperature of gf_set_temperature.  `reps` rounds visit
+   every shape in turn; a visit runs one untimed sweep and then times 3
+   back-to-back sweeps between two events, group by group as gf_sweep runs
+   them (gf_set_cache_budget); the smallest median wins.  The trial sweeps
+   run on the bound links; the links, the Coulomb accumulators, the sweep
+   indices and counts and the stop flags are saved to host memory before
+   and written back after, so the caller's state is unchanged.
+   *waves_per_site and *block (may be NULL) receive the choice (of the
+   precision doing most sweeps).  With a tuning cache (gf_set_tune_cache)
+   a table whose key is in the cache takes the stored shape without timing,
+   and new choices are added to the file.  Key: device architecture, gauge
+   group, gauge, storage, kernel table and the size class of the bound
+   configuration (half-sites over all units and the number of units, each
+   rounded to a power of two). */
 int gf_autotune(gf_handle h, int reps, int *waves_per_site, int *block);
+int gf_autotune_heatbath(gf_handle h, int reps, int *waves_per_site, int *block);
+
+/* File of persisted autotuning choices (one "key W B nt xcd" line each),
+   read now if it exists and rewritten (via a temporary file and rename)
+   after each tuning that adds a choice; NULL or "" turns the cache off.
+   GF_E_INVALID if the file cannot be written when a choice is added. */
+int gf_set_tune_cache(gf_handle h, const char *path);
 
 /* Kernel timing: every: 0 off; n >= 1 times half-sweep launches with HIP
    events that the launch itself records on the handle's stream.  Inside

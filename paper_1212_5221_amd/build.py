@@ -2,7 +2,8 @@
 
     python -m paper_1212_5221_amd.build        # or build() from Python
 
-Every .hip / .cpp under csrc/ is compiled with hipcc for gfx950 and linked
+Every .hip / .cpp under csrc/ is compiled with hipcc for gfx950 (the SU(3)
+half-sweep table gf_sweep_inst.hip once per gauge and storage) and linked
 into paper_1212_5221_amd/libgf.so.  Packed-FP32 instructions are disabled.
 """
 from __future__ import annotations
@@ -23,14 +24,18 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(os.path.dirname(HERE), "include")]
 
-SOURCES = ["gf_api.cpp", "gf_kernels.hip", "gf_sweep_landau.hip", "gf_sweep_coulomb.hip", "gf_sweep_mag.hip",
-           "gf_sweep_su2.hip", "gf_stream.hip"]
+SOURCES = ["gf_api.cpp", "gf_kernels.hip", "gf_sweep_su2.hip", "gf_stream.hip"]
+# the SU(3) half-sweep variants: gf_sweep_inst.hip once per gauge (Landau,
+# Coulomb, MAG) and storage (FP64-18, FP64-12, FP32-12, single precision)
+INST = [("gf_sweep_inst.hip", "gf_sweep_g%d_s%d.o" % (g, st), ["-DGF_GAUGE=%d" % g, "-DGF_STORAGE=%d" % st])
+        for g in range(3) for st in range(4)]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _compile(job) -> str:
+    src, objname, defs = job if isinstance(job, tuple) else (job, os.path.splitext(job)[0] + ".o", [])
+    obj = os.path.join(BUILD, objname)
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
-    cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + defs + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -41,9 +46,10 @@ def _compile(src: str) -> str:
 def build(jobs: int | None = None, verbose: bool = True) -> str:
     """Compile all sources (always) and link libgf.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 8)
+    work = INST + SOURCES  # the long instantiation units first
+    jobs = jobs or min(len(work), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(_compile, work))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.check_call(cmd)

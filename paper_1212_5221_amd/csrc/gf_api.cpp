@@ -10,12 +10,16 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
 #include "../../include/gf.h"
 #include "gf_launch.hpp"
 #include "gf_shared.hpp"
+#include "gf_variants.hpp"
 
 namespace {
 
@@ -24,6 +28,14 @@ struct InstHost {
     int64_t V, Vh, Vp;  // sites, half, half rounded up to 16
     int32_t unit0, nunits;
     int64_t links_off, g_off;
+};
+
+// Launch shape of one kernel table: W wavefronts per group of 64 sites, B
+// threads per block, non-temporal link traffic, XCD-contiguous tile order.
+struct Shape {
+    int W = 1, B = 256, nt = 0, xcd = 1;
+    bool operator==(const Shape &o) const { return W == o.W && B == o.B && nt == o.nt && xcd == o.xcd; }
+    int key() const { return ((gfl::wave_index(W) * 4 + gfl::block_index(B)) * 2 + nt) * 2 + xcd; }
 };
 
 // Graphs of chunks of sweeps, one per launch pattern: update, chunk length,
@@ -80,10 +92,12 @@ struct gf_ctx {
     int64_t max_tiles = 0;
     std::vector<gfs::UnitDev> units;
 
-    // launch configuration per tile table: 0 FP32 update, 1 FP64 update, 2
-    // heatbath (FP64): wavefronts per group of 64 sites and the matching
-    // sweep tile tables
-    int W[3] = {1, 1, 1};
+    // launch shape per kernel table (0 FP32 update, 1 FP64 update, 2
+    // heatbath) and the matching sweep tile tables
+    Shape shape[3];
+    // persisted autotuning choices: file and its entries (key -> shape)
+    std::string tune_path;
+    std::map<std::string, Shape> tune_cache;
     int ntiles[3] = {0, 0, 0};
     int force_ctd = -1;  // autotuning: time one precision only
 
@@ -293,10 +307,10 @@ gfs::InstDev inst_dev(const InstHost &I) {
     return d;
 }
 
-// sweep tile table `tab` (0 FP32 update, 1 FP64 update, 2 heatbath) for W
-// wavefronts per group of 64 sites
-int build_tiles(gf_ctx *h, int tab, int W) {
-    const int spb = gfl::SWEEP_THREADS / W;
+// sweep tile table `tab` (0 FP32 update, 1 FP64 update, 2 heatbath) for the
+// launch shape `sh`: tiles of B / W sites
+int build_tiles(gf_ctx *h, int tab, const Shape &sh) {
+    const int spb = sh.B / sh.W;
     std::vector<gfs::Tile> t;
     h->tile_u0[tab].assign(h->nunits + 1, 0);
     for (int u = 0; u < h->nunits; ++u) {
@@ -309,24 +323,58 @@ int build_tiles(gf_ctx *h, int tab, int W) {
                              h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->ntiles[tab] = (int)t.size();
-    h->W[tab] = W;
+    h->shape[tab] = sh;
     h->graph.clear();
     return GF_OK;
 }
 
-// default wavefronts per site group: FP32 update 1, FP64 update the largest
-// available of 4, 2, 1 (fewer links per wavefront, more waves in flight);
-// heatbath (table 2, measured at 32^4): 1 on FP32 storage, 2 on FP64-12, 4
-// on FP64-18 where available
-int default_W_for(const gf_ctx *h, int tab) {
+// the kernel that table `tab` launches for the OR update (heatbath table:
+// the heatbath) with shape sh, nullptr if not built.  A shape of the FP64
+// table must also have the stochastic-relaxation variant (cached), which
+// runs with that table's shape.
+gfl::sweep_fn table_kernel(const gf_ctx *h, int tab, const Shape &sh) {
     const int st = st_code(h);
-    if (tab == 0) return 1;
     const int upd = (tab == 2) ? gfs::UPD_HEATBATH : gfs::UPD_OR;
-    int first = 4;
-    if (tab == 2) first = (st == gfs::ST_F32R12) ? 1 : (st == gfs::ST_F64R12 ? 2 : 4);
-    for (int W = first; W >= 1; W /= 2)
-        if (gfl::sweep_kernel(h->gauge, upd, st, 1, W)) return W;
-    return 1;
+    const int ctd = (tab == 0) ? 0 : 1;
+    const int kst = (h->storage == GF_F32_R12 && ctd == 0)
+                        ? (h->nc == 2 ? (int)gfs::ST_SU2_F32_SP : (int)gfs::ST_F32R12_SP)
+                        : st;
+    if (tab == 1 && !gfl::sweep_kernel(h->gauge, gfs::UPD_SR, st, 1, sh.W, sh.B, 0)) return nullptr;
+    return gfl::sweep_kernel(h->gauge, upd, kst, ctd, sh.W, sh.B, sh.nt);
+}
+
+// every shape table `tab` can launch
+std::vector<Shape> table_shapes(const gf_ctx *h, int tab) {
+    std::vector<Shape> v;
+    for (int xcd = 1; xcd >= 0; --xcd)
+        for (int nt = 0; nt < gfl::NNT; ++nt)
+            for (int wi = 0; wi < gfl::NWAVE; ++wi)
+                for (int bi = 0; bi < gfl::NBLOCK; ++bi) {
+                    Shape sh;
+                    sh.W = gfl::wave_of(wi);
+                    sh.B = gfl::block_of(bi);
+                    sh.nt = nt;
+                    sh.xcd = xcd;
+                    if (table_kernel(h, tab, sh)) v.push_back(sh);
+                }
+    return v;
+}
+
+// default shape: 256 threads, cached, XCD order; W for the FP32 update 1,
+// for the FP64 update the largest available of 4, 2, 1 (fewer links per
+// wavefront, more waves in flight); heatbath (measured at 32^4): 1 on FP32
+// storage, 2 on FP64-12, 4 on FP64-18 where available
+Shape default_shape(const gf_ctx *h, int tab) {
+    const int st = st_code(h);
+    Shape sh;
+    if (tab == 0) return sh;
+    const int first = (tab == 2) ? ((st == gfs::ST_F32R12) ? 1 : (st == gfs::ST_F64R12 ? 2 : 4)) : 4;
+    for (int W = first; W >= 1; W /= 2) {
+        sh.W = W;
+        if (table_kernel(h, tab, sh)) return sh;
+    }
+    sh.W = 1;
+    return sh;
 }
 
 int check_bound(gf_ctx *h) {
@@ -384,7 +432,7 @@ gfs::SweepArgs sweep_args(gf_ctx *h, int parity, int fp64_select, double T, int 
     a.parity = parity;
     a.fp64_select = fp64_select;
     a.sweep_off = sweep_off;
-    a.pad = 0;
+    a.xcd_order = 1;
     a.omega = h->omega;
     a.T = T;
     a.p_sr = h->p_sr;
@@ -455,11 +503,15 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
         const int ctd = launches[k].ctd, tab = launches[k].tab;
         // single precision: the FP32-update kernels that also apply G in FP32
         const int kst = (single && ctd == 0) ? (h->nc == 2 ? (int)gfs::ST_SU2_F32_SP : (int)gfs::ST_F32R12_SP) : st;
-        gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, kst, ctd, h->W[tab]);
-        if (!fn) return fail(h, GF_E_INVALID, "no kernel variant for gauge %d update %d storage %d W %d", h->gauge, upd,
-                             h->storage, h->W[tab]);
+        const Shape &sh = h->shape[tab];
+        // the random updates have cached variants only
+        gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, kst, ctd, sh.W, sh.B, gfl::is_random(upd) ? 0 : sh.nt);
+        if (!fn)
+            return fail(h, GF_E_INVALID, "no kernel variant for gauge %d update %d storage %d W %d B %d", h->gauge,
+                        upd, h->storage, sh.W, sh.B);
         int nt = 0;
         gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T, tab, sweep_off, grp, &nt);
+        a.xcd_order = sh.xcd;
         if (nt <= 0) continue;
         const bool tm = h->timing && !capturing && h->time_now;
         if (tm) {
@@ -467,15 +519,15 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
             hipEvent_t e0 = take_event(h), e1 = take_event(h);
             if (!e0 || !e1) return fail(h, GF_E_HIP, "hipEventCreate failed");
             void *args[] = {&a};
-            HIPCHK(h, hipExtLaunchKernel(reinterpret_cast<const void *>(fn), dim3((unsigned)nt),
-                                         dim3(gfl::SWEEP_THREADS), args, 0, h->cur, e0, e1, 0));
+            HIPCHK(h, hipExtLaunchKernel(reinterpret_cast<const void *>(fn), dim3((unsigned)nt), dim3((unsigned)sh.B),
+                                         args, 0, h->cur, e0, e1, 0));
             h->ev_pending.push_back({e0, e1, launches[k].ctd});
             if (h->ev_pending.size() > 4096) {
                 int rc = drain_timing(h);
                 if (rc) return rc;
             }
         } else {
-            fn<<<dim3((unsigned)nt), dim3(gfl::SWEEP_THREADS), 0, h->cur>>>(a);
+            fn<<<dim3((unsigned)nt), dim3((unsigned)sh.B), 0, h->cur>>>(a);
             HIPCHK(h, hipGetLastError());
         }
     }
@@ -591,7 +643,7 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
     int tailkey = 0;
     if (h->storage == GF_MIXED_F32_R12 && h->tail_theta > 0.0)
         tailkey = (h->n_tail == 0) ? 1 : (h->n_tail >= h->n_active ? 2 : 3);
-    const int wkey = (h->W[0] * 16 + h->W[1]) * 16 + h->W[2];
+    const int wkey = (h->shape[0].key() * 64 + h->shape[1].key()) * 64 + h->shape[2].key();
     // which sweeps of the chunk reproject: none or one (R >= n, keyed by the
     // position), or a pattern fixed by k0 mod R (R < n)
     int rkey = -1;
@@ -657,11 +709,21 @@ int check_inst(gf_ctx *h, int32_t inst) {
 }  // namespace
 
 namespace gfl {
-sweep_fn sweep_kernel(int gauge, int upd, int st, int ct_double, int W) {
-    if (gfs::is_su2(st)) return sweep_kernel_su2(gauge, upd, st, ct_double, W);
-    if (gauge == gfs::LANDAU) return sweep_kernel_landau(upd, st, ct_double, W);
-    if (gauge == gfs::COULOMB) return sweep_kernel_coulomb(upd, st, ct_double, W);
-    return sweep_kernel_mag(upd, st, ct_double, W);
+template <int G>
+static sweep_fn su3_by_storage(int upd, int st, int ctd, int wi, int bi, int nt) {
+    if (st == gfs::ST_F64R18) return su3_lookup<G, gfs::ST_F64R18>(upd, ctd, wi, bi, nt);
+    if (st == gfs::ST_F64R12) return su3_lookup<G, gfs::ST_F64R12>(upd, ctd, wi, bi, nt);
+    if (st == gfs::ST_F32R12) return su3_lookup<G, gfs::ST_F32R12>(upd, ctd, wi, bi, nt);
+    return su3_lookup<G, gfs::ST_F32R12_SP>(upd, ctd, wi, bi, nt);
+}
+
+sweep_fn sweep_kernel(int gauge, int upd, int st, int ct_double, int W, int B, int nt) {
+    if (gfs::is_su2(st)) return sweep_kernel_su2(gauge, upd, st, ct_double, W, B, nt);
+    if (upd < 0 || upd >= NUPD || !su3_built(gauge, upd, st, ct_double, W, B, nt)) return nullptr;
+    const int wi = wave_index(W), bi = block_index(B);
+    if (gauge == gfs::LANDAU) return su3_by_storage<gfs::LANDAU>(upd, st, ct_double, wi, bi, nt);
+    if (gauge == gfs::COULOMB) return su3_by_storage<gfs::COULOMB>(upd, st, ct_double, wi, bi, nt);
+    return su3_by_storage<gfs::MAG>(upd, st, ct_double, wi, bi, nt);
 }
 }  // namespace gfl
 
@@ -813,9 +875,9 @@ int gf_bind_workspace(gf_handle h, void *dev_ptr, size_t bytes) {
     h->n_tail = (h->tail_theta >= 1e300) ? h->nunits : 0;
     h->bound = true;
     build_groups(h);
-    rc = build_tiles(h, 0, default_W_for(h, 0));
-    if (rc == GF_OK) rc = build_tiles(h, 1, default_W_for(h, 1));
-    if (rc == GF_OK) rc = build_tiles(h, 2, default_W_for(h, 2));
+    rc = build_tiles(h, 0, default_shape(h, 0));
+    if (rc == GF_OK) rc = build_tiles(h, 1, default_shape(h, 1));
+    if (rc == GF_OK) rc = build_tiles(h, 2, default_shape(h, 2));
     if (rc) {
         h->bound = false;
         return rc;
@@ -1207,99 +1269,281 @@ static int used_precisions(const gf_ctx *h) {
 // the precision doing most of the sweeps
 static int dominant_ctd(const gf_ctx *h) { return (used_precisions(h) & 1) ? 0 : 1; }
 
-int gf_set_launch(gf_handle h, int lanes_per_site, int block) {
-    int rc = check_bound(h);
-    if (rc) return rc;
-    if (block != 0 && block != gfl::SWEEP_THREADS) return fail(h, GF_E_INVALID, "block %d not available", block);
-    const int st = st_code(h);
-    int set = 0;
-    for (int tab = 0; tab < 3; ++tab) {
-        const int W = lanes_per_site == 0 ? default_W_for(h, tab) : lanes_per_site;
-        const int upd = (tab == 2) ? gfs::UPD_HEATBATH : gfs::UPD_OR;
-        if (!gfl::sweep_kernel(h->gauge, upd, st, tab == 0 ? 0 : 1, W)) continue;
-        rc = build_tiles(h, tab, W);
-        if (rc) return rc;
-        ++set;
-    }
-    if (!set) return fail(h, GF_E_INVALID, "no variant with %d wavefronts per site group", lanes_per_site);
+static int check_table(gf_ctx *h, int kernels) {
+    if (kernels < GF_KERNELS_FP32 || kernels > GF_KERNELS_HEATBATH)
+        return fail(h, GF_E_INVALID, "kernel table %d (GF_KERNELS_FP32, _FP64 or _HEATBATH)", kernels);
     return GF_OK;
 }
 
-int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
+int gf_set_launch(gf_handle h, int lanes_per_site, int block) {
     int rc = check_bound(h);
     if (rc) return rc;
-    if (reps < 1) reps = 1;
-    const int st = st_code(h);
-    rc = drain_timing(h);
+    if (block != 0 && gfl::block_index(block) < 0) return fail(h, GF_E_INVALID, "block %d not available", block);
+    int set = 0;
+    for (int tab = 0; tab < 3; ++tab) {
+        Shape sh;
+        sh.W = lanes_per_site == 0 ? default_shape(h, tab).W : lanes_per_site;
+        sh.B = block == 0 ? 256 : block;
+        if (!table_kernel(h, tab, sh)) continue;
+        rc = build_tiles(h, tab, sh);
+        if (rc) return rc;
+        ++set;
+    }
+    if (!set)
+        return fail(h, GF_E_INVALID, "no variant with %d wavefronts per site group and %d threads per block",
+                    lanes_per_site, block);
+    return GF_OK;
+}
+
+int gf_set_shape(gf_handle h, int kernels, int waves_per_site, int block, int flags) {
+    int rc = check_bound(h);
     if (rc) return rc;
+    rc = check_table(h, kernels);
+    if (rc) return rc;
+    if (flags & ~(GF_SHAPE_NONTEMPORAL | GF_SHAPE_LINEAR_TILES)) return fail(h, GF_E_INVALID, "flags %d", flags);
+    Shape sh;
+    sh.W = waves_per_site;
+    sh.B = block;
+    sh.nt = (flags & GF_SHAPE_NONTEMPORAL) ? 1 : 0;
+    sh.xcd = (flags & GF_SHAPE_LINEAR_TILES) ? 0 : 1;
+    if (!table_kernel(h, kernels, sh))
+        return fail(h, GF_E_INVALID, "no variant of kernel table %d with W %d, B %d, flags %d", kernels,
+                    waves_per_site, block, flags);
+    return build_tiles(h, kernels, sh);
+}
+
+int gf_get_shape(gf_handle h, int kernels, int *waves_per_site, int *block, int *flags) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    rc = check_table(h, kernels);
+    if (rc) return rc;
+    const Shape &sh = h->shape[kernels];
+    if (waves_per_site) *waves_per_site = sh.W;
+    if (block) *block = sh.B;
+    if (flags) *flags = (sh.nt ? GF_SHAPE_NONTEMPORAL : 0) | (sh.xcd ? 0 : GF_SHAPE_LINEAR_TILES);
+    return GF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotuning
+namespace {
+
+// what a tuning key holds: device architecture, gauge group, gauge, storage,
+// kernel table, and the size class of the bound configuration (half-sites
+// and units, each rounded to a power of two)
+std::string tune_key(gf_ctx *h, int tab) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, h->dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t c = arch.find(':');
+        if (c != std::string::npos) arch = arch.substr(0, c);
+    }
+    int64_t hs = 0;
+    for (const auto &u : h->units) hs += u.n;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s/su%d/gauge%d/storage%d/kernels%d/halfsites2^%ld/units2^%ld", arch.c_str(), h->nc,
+             h->gauge, h->storage, tab, std::lround(std::log2((double)std::max<int64_t>(hs, 1))),
+             std::lround(std::log2((double)std::max(h->nunits, 1))));
+    return buf;
+}
+
+int load_tune_cache(gf_ctx *h) {
+    h->tune_cache.clear();
+    std::ifstream f(h->tune_path);
+    if (!f) return GF_OK;  // no file yet
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string key;
+        Shape sh;
+        if (!(is >> key >> sh.W >> sh.B >> sh.nt >> sh.xcd)) continue;
+        if (gfl::wave_index(sh.W) < 0 || gfl::block_index(sh.B) < 0 || (sh.nt & ~1) || (sh.xcd & ~1)) continue;
+        h->tune_cache[key] = sh;
+    }
+    return GF_OK;
+}
+
+int save_tune_cache(gf_ctx *h) {
+    const std::string tmp = h->tune_path + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        if (!f) return fail(h, GF_E_INVALID, "cannot write the tuning cache %s", tmp.c_str());
+        for (const auto &kv : h->tune_cache)
+            f << kv.first << ' ' << kv.second.W << ' ' << kv.second.B << ' ' << kv.second.nt << ' ' << kv.second.xcd
+              << '\n';
+        if (!f) return fail(h, GF_E_INVALID, "cannot write the tuning cache %s", tmp.c_str());
+    }
+    if (std::rename(tmp.c_str(), h->tune_path.c_str()) != 0)
+        return fail(h, GF_E_INVALID, "cannot replace the tuning cache %s", h->tune_path.c_str());
+    return GF_OK;
+}
+
+// The state trial sweeps change: the link planes and Coulomb accumulators
+// (workspace [0, off_inst)) and the per-unit results, stop and tail flags,
+// sweep counts and sweep indices ([off_res, off_status + 256)).  Saved to
+// host memory and written back, so tuning leaves the caller's state as it
+// was.
+struct Snapshot {
+    std::vector<char> lat, book;
+    int n_active = 0, n_tail = 0;
+};
+
+int save_state(gf_ctx *h, Snapshot &sn) {
+    sn.lat.resize(h->off_inst);
+    sn.book.resize(h->off_status + 256 - h->off_res);
+    HIPCHK(h, hipMemcpyAsync(sn.lat.data(), h->ws, sn.lat.size(), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(sn.book.data(), h->ws + h->off_res, sn.book.size(), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    sn.n_active = h->n_active;
+    sn.n_tail = h->n_tail;
+    return GF_OK;
+}
+
+int restore_state(gf_ctx *h, const Snapshot &sn) {
+    HIPCHK(h, hipMemcpyAsync(h->ws, sn.lat.data(), sn.lat.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_res, sn.book.data(), sn.book.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->n_active = sn.n_active;
+    h->n_tail = sn.n_tail;
+    return GF_OK;
+}
+
+// Time every shape of table `tab` with update `upd` and keep the fastest.
+// Rounds interleave the shapes (drifts of clock or temperature hit all of
+// them alike).  A visit switches the shape, runs one untimed sweep, then
+// times kSweeps back-to-back sweeps between two events, group by group as
+// gf_sweep runs them, so the figure is the sweep throughput including launch
+// gaps.  The smallest median wins.  All units are active during the trial.
+int time_shapes(gf_ctx *h, int tab, int upd, int reps, hipEvent_t e0, hipEvent_t e1, Shape *best) {
+    constexpr int kSweeps = 3;
+    const std::vector<Shape> cand = table_shapes(h, tab);
+    if (cand.empty()) return fail(h, GF_E_INVALID, "kernel table %d has no variant", tab);
+    std::vector<std::vector<float>> times(cand.size());
+    HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_active), 1, h->nunits, h->stream));
+    h->n_active = h->nunits;
+    for (int r = 0; r < reps; ++r)
+        for (size_t k = 0; k < cand.size(); ++k) {
+            int rc = build_tiles(h, tab, cand[k]);
+            if (rc == GF_OK) rc = enqueue_chunk(h, upd, 1, 0, false);
+            if (rc == GF_OK) rc = count_chunk(h, 1);
+            if (rc) return rc;
+            HIPCHK(h, hipEventRecord(e0, h->cur));
+            rc = enqueue_chunk(h, upd, kSweeps, 0, false);
+            if (rc == GF_OK) rc = count_chunk(h, kSweeps);
+            if (rc) return rc;
+            HIPCHK(h, hipEventRecord(e1, h->cur));
+            HIPCHK(h, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+            times[k].push_back(ms / kSweeps);
+        }
+    double bt = 1e300;
+    for (size_t k = 0; k < cand.size(); ++k) {
+        std::vector<float> &t = times[k];
+        std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+        const double med = t[t.size() / 2];
+        if (med < bt) {
+            bt = med;
+            *best = cand[k];
+        }
+    }
+    return GF_OK;
+}
+
+// tune tables `tabs` (with update upd), from the cache where it has them
+int autotune_tables(gf_ctx *h, const std::vector<int> &tabs, int upd, int reps) {
+    if (reps < 1) reps = 1;
+    int rc = drain_timing(h);
+    if (rc) return rc;
+    std::vector<int> todo;
+    for (int tab : tabs) {
+        auto it = h->tune_path.empty() ? h->tune_cache.end() : h->tune_cache.find(tune_key(h, tab));
+        if (it != h->tune_cache.end() && table_kernel(h, tab, it->second)) {
+            rc = build_tiles(h, tab, it->second);
+            if (rc) return rc;
+        } else {
+            todo.push_back(tab);
+        }
+    }
+    if (todo.empty()) return GF_OK;
     hipEvent_t e0 = take_event(h), e1 = take_event(h);
     if (!e0 || !e1) return fail(h, GF_E_HIP, "hipEventCreate failed");
-    // trial sweeps are plain launches (no per-launch events); the caller's
-    // timing state and the events come back on every return path
+    // trial sweeps are plain launches without reprojection or per-launch
+    // events; the caller's settings and the events come back on every path
     struct Restore {
         gf_ctx *h;
         bool timing;
+        int reunit_every;
         hipEvent_t e0, e1;
         ~Restore() {
             h->timing = timing;
+            h->reunit_every = reunit_every;
             h->force_ctd = -1;
             h->ev_pool.push_back(e0);
             h->ev_pool.push_back(e1);
         }
-    } restore{h, h->timing, e0, e1};
+    } restore{h, h->timing, h->reunit_every, e0, e1};
     h->timing = false;
-    HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_active), 1, h->nunits, h->stream));
-    const int used = used_precisions(h);
-    // Rounds interleave the candidate shapes (drifts of clock or temperature
-    // hit all of them alike).  A visit switches the shape, runs one untimed
-    // OR sweep, then times kSweeps back-to-back OR sweeps between two events
-    // (real sweeps: they advance the fixing), so the figure is the sweep
-    // throughput including launch gaps.  The smallest median wins.
-    constexpr int kSweeps = 3;
-    for (int ctd = 0; ctd < 2; ++ctd) {
-        if (!(used & (1 << ctd))) continue;
-        std::vector<int> Ws;
-        for (int W = 1; W <= 8; W *= 2)
-            if (gfl::sweep_kernel(h->gauge, gfs::UPD_OR, st, ctd, W)) Ws.push_back(W);
-        std::vector<std::vector<float>> times(Ws.size());
-        h->force_ctd = ctd;
-        for (int r = 0; r < reps; ++r)
-            for (size_t k = 0; k < Ws.size(); ++k) {
-                rc = build_tiles(h, ctd, Ws[k]);
-                if (rc == GF_OK) rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false, 0);
-                if (rc == GF_OK) rc = count_chunk(h, 1);
-                if (rc) return rc;
-                HIPCHK(h, hipEventRecord(e0, h->cur));
-                for (int i = 0; i < kSweeps && rc == GF_OK; ++i) {
-                    rc = launch_sweep(h, gfs::UPD_OR, h->T, false, false, 0);
-                    if (rc == GF_OK) rc = count_chunk(h, 1);
-                }
-                if (rc) return rc;
-                HIPCHK(h, hipEventRecord(e1, h->cur));
-                HIPCHK(h, hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
-                times[k].push_back(ms / kSweeps);
-            }
+    h->reunit_every = 0;
+    Snapshot sn;
+    rc = save_state(h, sn);
+    if (rc) return rc;
+    std::vector<Shape> best(todo.size());
+    for (size_t i = 0; i < todo.size() && rc == GF_OK; ++i) {
+        h->force_ctd = (upd == gfs::UPD_HEATBATH) ? -1 : todo[i];
+        rc = time_shapes(h, todo[i], upd, reps, e0, e1, &best[i]);
         h->force_ctd = -1;
-        int bestW = h->W[ctd];
-        double best = 1e300;
-        for (size_t k = 0; k < Ws.size(); ++k) {
-            std::vector<float> &t = times[k];
-            if (t.empty()) continue;
-            std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
-            const double med = t[t.size() / 2];
-            if (med < best) {
-                best = med;
-                bestW = Ws[k];
-            }
-        }
-        rc = build_tiles(h, ctd, bestW);
-        if (rc) return rc;
     }
-    if (lanes_per_site) *lanes_per_site = h->W[dominant_ctd(h)];
-    if (block) *block = gfl::SWEEP_THREADS;
+    const int rs = restore_state(h, sn);
+    if (rc) return rc;
+    if (rs) return rs;
+    for (size_t i = 0; i < todo.size(); ++i) {
+        rc = build_tiles(h, todo[i], best[i]);
+        if (rc) return rc;
+        if (!h->tune_path.empty()) h->tune_cache[tune_key(h, todo[i])] = best[i];
+    }
+    if (!h->tune_path.empty()) return save_tune_cache(h);
     return GF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gf_autotune(gf_handle h, int reps, int *lanes_per_site, int *block) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    const int used = used_precisions(h);
+    std::vector<int> tabs;
+    for (int ctd = 0; ctd < 2; ++ctd)
+        if (used & (1 << ctd)) tabs.push_back(ctd);
+    rc = autotune_tables(h, tabs, gfs::UPD_OR, reps);
+    if (rc) return rc;
+    if (lanes_per_site) *lanes_per_site = h->shape[dominant_ctd(h)].W;
+    if (block) *block = h->shape[dominant_ctd(h)].B;
+    return GF_OK;
+}
+
+int gf_autotune_heatbath(gf_handle h, int reps, int *lanes_per_site, int *block) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    rc = autotune_tables(h, {2}, gfs::UPD_HEATBATH, reps);
+    if (rc) return rc;
+    if (lanes_per_site) *lanes_per_site = h->shape[2].W;
+    if (block) *block = h->shape[2].B;
+    return GF_OK;
+}
+
+int gf_set_tune_cache(gf_handle h, const char *path) {
+    if (!h) return GF_E_INVALID;
+    h->tune_path = path ? path : "";
+    if (h->tune_path.empty()) {
+        h->tune_cache.clear();
+        return GF_OK;
+    }
+    return load_tune_cache(h);
 }
 
 int gf_set_timing(gf_handle h, int every) {

@@ -215,6 +215,48 @@ __device__ __forceinline__ V *site_vec(V *base, uint32_t h) {
     return base + (size_t)(h >> 4) * (NCH * 16) + (h & 15u);
 }
 
+// one 16-byte vector access; NT: non-temporal (streaming) cache policy
+// (the builtins take native vector types)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <bool NT>
+__device__ __forceinline__ float4 ld16(const float4 *p) {
+    if constexpr (NT) {
+        const f32x4 n = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
+        return make_float4(n.x, n.y, n.z, n.w);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ double2 ld16(const double2 *p) {
+    if constexpr (NT) {
+        const f64x2 n = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p));
+        return make_double2(n.x, n.y);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void st16(float4 *p, const float4 &v) {
+    if constexpr (NT) {
+        f32x4 n = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(n, reinterpret_cast<f32x4 *>(p));
+    } else {
+        *p = v;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void st16(double2 *p, const double2 &v) {
+    if constexpr (NT) {
+        f64x2 n = {v.x, v.y};
+        __builtin_nontemporal_store(n, reinterpret_cast<f64x2 *>(p));
+    } else {
+        *p = v;
+    }
+}
+
 template <int ST>
 struct Store;
 
@@ -223,21 +265,23 @@ struct Store<gfs::ST_F32R12> {
     typedef float S;
     typedef float4 V;
     static constexpr int NR = 12, NCH = 3, ROWS = 2;
+    template <bool NT = false>
     __device__ static __forceinline__ void load(const V *__restrict__ base, int64_t Vh, int64_t h, S r[NR]) {
         const V *sv = site_vec<NCH>(base, (uint32_t)h);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            V v = sv[16 * c];
+            V v = ld16<NT>(sv + 16 * c);
             r[4 * c] = v.x;
             r[4 * c + 1] = v.y;
             r[4 * c + 2] = v.z;
             r[4 * c + 3] = v.w;
         }
     }
+    template <bool NT = false>
     __device__ static __forceinline__ void store(V *__restrict__ base, int64_t Vh, int64_t h, const S r[NR]) {
         V *sv = site_vec<NCH>(base, (uint32_t)h);
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) sv[16 * c] = make_float4(r[4 * c], r[4 * c + 1], r[4 * c + 2], r[4 * c + 3]);
+        for (int c = 0; c < NCH; ++c) st16<NT>(sv + 16 * c, make_float4(r[4 * c], r[4 * c + 1], r[4 * c + 2], r[4 * c + 3]));
     }
 };
 
@@ -249,19 +293,21 @@ struct Store<gfs::ST_F64R12> {
     typedef double S;
     typedef double2 V;
     static constexpr int NR = 12, NCH = 6, ROWS = 2;
+    template <bool NT = false>
     __device__ static __forceinline__ void load(const V *__restrict__ base, int64_t Vh, int64_t h, S r[NR]) {
         const V *sv = site_vec<NCH>(base, (uint32_t)h);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            V v = sv[16 * c];
+            V v = ld16<NT>(sv + 16 * c);
             r[2 * c] = v.x;
             r[2 * c + 1] = v.y;
         }
     }
+    template <bool NT = false>
     __device__ static __forceinline__ void store(V *__restrict__ base, int64_t Vh, int64_t h, const S r[NR]) {
         V *sv = site_vec<NCH>(base, (uint32_t)h);
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) sv[16 * c] = make_double2(r[2 * c], r[2 * c + 1]);
+        for (int c = 0; c < NCH; ++c) st16<NT>(sv + 16 * c, make_double2(r[2 * c], r[2 * c + 1]));
     }
 };
 
@@ -270,19 +316,21 @@ struct Store<gfs::ST_F64R18> {
     typedef double S;
     typedef double2 V;
     static constexpr int NR = 18, NCH = 9, ROWS = 3;
+    template <bool NT = false>
     __device__ static __forceinline__ void load(const V *__restrict__ base, int64_t Vh, int64_t h, S r[NR]) {
         const V *sv = site_vec<NCH>(base, (uint32_t)h);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            V v = sv[16 * c];
+            V v = ld16<NT>(sv + 16 * c);
             r[2 * c] = v.x;
             r[2 * c + 1] = v.y;
         }
     }
+    template <bool NT = false>
     __device__ static __forceinline__ void store(V *__restrict__ base, int64_t Vh, int64_t h, const S r[NR]) {
         V *sv = site_vec<NCH>(base, (uint32_t)h);
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) sv[16 * c] = make_double2(r[2 * c], r[2 * c + 1]);
+        for (int c = 0; c < NCH; ++c) st16<NT>(sv + 16 * c, make_double2(r[2 * c], r[2 * c + 1]));
     }
 };
 

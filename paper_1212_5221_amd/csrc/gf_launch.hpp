@@ -9,15 +9,17 @@
 namespace gfl {
 
 // the half-sweep kernel variant for (gauge, update, storage, compute in
-// double?, waves per site group); nullptr if not built
+// double?) and launch shape (W wavefronts per site group, B threads per
+// block, non-temporal link traffic nt); nullptr if not built (the variants
+// are those gf_variants.hpp declares built)
 typedef void (*sweep_fn)(gfs::SweepArgs);
-sweep_fn sweep_kernel(int gauge, int upd, int st, int ct_double, int W);
-sweep_fn sweep_kernel_landau(int upd, int st, int ct_double, int W);
-sweep_fn sweep_kernel_coulomb(int upd, int st, int ct_double, int W);
-sweep_fn sweep_kernel_mag(int upd, int st, int ct_double, int W);
-// gauge group SU(2) (storages ST_SU2_*; W = 1 only)
-sweep_fn sweep_kernel_su2(int gauge, int upd, int st, int ct_double, int W);
-constexpr int SWEEP_THREADS = 256;
+sweep_fn sweep_kernel(int gauge, int upd, int st, int ct_double, int W, int B, int nt);
+// the SU(3) table of one gauge and storage (gf_sweep_table.hpp), indexed by
+// the positions of W and B in their dimensions
+template <int G, int ST>
+sweep_fn su3_lookup(int upd, int ctd, int wi, int bi, int nt);
+// gauge group SU(2) (storages ST_SU2_*; W = 1, nt = 0)
+sweep_fn sweep_kernel_su2(int gauge, int upd, int st, int ct_double, int W, int B, int nt);
 
 hipError_t measure(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a);
 // unit sums -> F = sum / (nc ndir V_u), theta = sum / (nc V_u) (nc: 3 or 2)

@@ -73,7 +73,7 @@ struct SweepArgs {
     int32_t parity;           // active parity (Coulomb: 3D parity)
     int32_t fp64_select;      // -1 all units, else only units whose flag equals it
     int32_t sweep_off;        // random counter = sweep_ix[inst] + sweep_off (sweeps counted per chunk)
-    int32_t pad;
+    int32_t xcd_order;        // 1: block b works on tile xcd_tile(b, n) (contiguous per XCD), 0: on tile b
     double omega, T, p_sr;
     uint64_t seed;
 };

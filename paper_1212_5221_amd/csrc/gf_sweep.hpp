@@ -25,7 +25,6 @@
 
 namespace gfd {
 
-constexpr int SWEEP_BLOCK = 256;
 
 // ---------------------------------------------------------------- updates
 template <typename T>
@@ -359,8 +358,11 @@ __device__ __forceinline__ void apply_right_dag(const M3<T> &G, const M3<T> &U, 
 }
 
 // ---------------------------------------------------------------- kernel
-template <int GAUGE, int UPD, int ST, typename CT, int W>
-__global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
+// BLK threads per block (BLK / (64 W) site groups); NT: non-temporal loads
+// and stores of the links (streaming past the caches, for lattices larger
+// than the Infinity Cache)
+template <int GAUGE, int UPD, int ST, typename CT, int W, int BLK, int NT>
+__global__ __launch_bounds__(BLK) void k_sweep(gfs::SweepArgs a) {
     typedef Store<ST> SD;
     typedef typename SD::S S;
     typedef typename SD::V V;
@@ -369,12 +371,12 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
     constexpr int NL = 2 * NDIR;
     constexpr int LPW = NL / W;
     static_assert(NL % W == 0, "waves must split the links evenly");
-    constexpr int GROUPS = SWEEP_BLOCK / (64 * W);
+    constexpr int GROUPS = BLK / (64 * W);
     static_assert(GROUPS >= 1, "block too small");
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wv = wave % W, grp = wave / W;
-    const gfs::Tile tl = a.tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const gfs::Tile tl = a.tiles[a.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x];
     const int u = tl.unit;
     if (!a.active[u]) return;
     if (a.fp64_select >= 0 && a.fp64[u] != a.fp64_select) return;
@@ -398,7 +400,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
         const bool fw = l < NDIR;
         const int mu = MU0 + (fw ? l : l - NDIR);
         lh[q] = fw ? h : back_h(I, s, h, mu);
-        SD::load(plane_ptr<ST>(a.ws, I, fw ? p : 1 - p, mu), I.Vh, lh[q], r[q]);
+        SD::template load<NT != 0>(plane_ptr<ST>(a.ws, I, fw ? p : 1 - p, mu), I.Vh, lh[q], r[q]);
     }
 
     Rng rng;
@@ -571,7 +573,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
             apply_right_dag(Ga, m, o, SD::ROWS);
         }
         compress<ST, AT>(o, r[q]);
-        if (valid) SD::store(plane_ptr<ST>(a.ws, I, fw ? p : 1 - p, mu), I.Vh, lh[q], r[q]);
+        if (valid) SD::template store<NT != 0>(plane_ptr<ST>(a.ws, I, fw ? p : 1 - p, mu), I.Vh, lh[q], r[q]);
     }
 
     // ---- Coulomb: accumulate G(x) <- G G(x) (wave 0 of the group)
@@ -579,13 +581,13 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(gfs::SweepArgs a) {
       if (wv == 0) {
         V *gp = gacc_ptr<ST>(a.ws, I, p);
         S gr[SD::NR];
-        SD::load(gp, I.Vh, h, gr);
+        SD::template load<NT != 0>(gp, I.Vh, h, gr);
         M3<AT> m, o;
         expand<ST, AT>(gr, m);
         apply_left(Ga, m, o, SD::ROWS);
         if constexpr (SD::ROWS == 2) renormalise_rows(o);
         compress<ST, AT>(o, gr);
-        if (valid) SD::store(gp, I.Vh, h, gr);
+        if (valid) SD::template store<NT != 0>(gp, I.Vh, h, gr);
       }
     }
 }

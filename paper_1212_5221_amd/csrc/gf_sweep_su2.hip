@@ -9,9 +9,14 @@
 // FP64 as two 16-byte chunks (u0, u1), (u2, u3); FP32 as one float4.  A site
 // of the active parity reads and writes its 8 (Coulomb 6) links once:
 // 256 bytes (FP32) or 512 bytes (FP64) of traffic per site update.
+#include <array>
+#include <type_traits>
+#include <utility>
+
 #include "gf_launch.hpp"
 #include "gf_reduce.hpp"
 #include "gf_sweep.hpp"
+#include "gf_variants.hpp"
 
 namespace gfd {
 
@@ -92,8 +97,8 @@ __device__ __forceinline__ void su2_mag_add(const Q4<T> &u, bool fwd, T &D, T &E
 // One thread per site of the active parity (no wave split: the 8 links are
 // 32 or 64 registers).  The local g is computed in CT; on FP32 storage it is
 // normalised and applied in FP64 (single precision: applied in FP32).
-template <int GAUGE, int UPD, int ST, typename CT>
-__global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep_su2(gfs::SweepArgs a) {
+template <int GAUGE, int UPD, int ST, typename CT, int BLK>
+__global__ __launch_bounds__(BLK) void k_sweep_su2(gfs::SweepArgs a) {
     typedef Store<ST> SD;
     typedef typename SD::S S;
     typedef typename SD::V V;
@@ -101,7 +106,7 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep_su2(gfs::SweepArgs a) {
     constexpr int MU0 = (GAUGE == gfs::COULOMB) ? 1 : 0;
     constexpr int NL = 2 * NDIR;
 
-    const gfs::Tile tl = a.tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const gfs::Tile tl = a.tiles[a.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x];
     const int u = tl.unit;
     if (!a.active[u]) return;
     if (a.fp64_select >= 0 && a.fp64[u] != a.fp64_select) return;
@@ -404,38 +409,45 @@ namespace gfl {
 
 using namespace gfd;
 
-template <int G>
-static sweep_fn su2_variant(int upd, int st, int ctd) {
-    if (st == gfs::ST_SU2_F64) {
-        if (!ctd) return nullptr;
-        if (upd == gfs::UPD_OR) return &k_sweep_su2<G, gfs::UPD_OR, gfs::ST_SU2_F64, double>;
-        if (upd == gfs::UPD_MICRO) return &k_sweep_su2<G, gfs::UPD_MICRO, gfs::ST_SU2_F64, double>;
-        if (upd == gfs::UPD_HEATBATH) return &k_sweep_su2<G, gfs::UPD_HEATBATH, gfs::ST_SU2_F64, double>;
-        if (upd == gfs::UPD_SR) return &k_sweep_su2<G, gfs::UPD_SR, gfs::ST_SU2_F64, double>;
+constexpr int NSUB2 = NUPD * NCTD * NBLOCK;
+
+template <int G, int ST, int I>
+sweep_fn su2_entry() {
+    constexpr int upd = I % NUPD;
+    constexpr int ctd = (I / NUPD) % NCTD;
+    constexpr int bi = I / (NUPD * NCTD);
+    if constexpr (su2_built(upd, ST, ctd, 1, block_of(bi), 0)) {
+        typedef typename std::conditional<ctd == 1, double, float>::type CT;
+        return &k_sweep_su2<G, upd, ST, CT, block_of(bi)>;
+    } else {
         return nullptr;
     }
-    if (st == gfs::ST_SU2_F32_SP) {
-        if (ctd) return nullptr;
-        if (upd == gfs::UPD_OR) return &k_sweep_su2<G, gfs::UPD_OR, gfs::ST_SU2_F32_SP, float>;
-        if (upd == gfs::UPD_MICRO) return &k_sweep_su2<G, gfs::UPD_MICRO, gfs::ST_SU2_F32_SP, float>;
-        return nullptr;
-    }
-    if (st != gfs::ST_SU2_F32) return nullptr;
-    if (upd == gfs::UPD_OR) return ctd ? &k_sweep_su2<G, gfs::UPD_OR, gfs::ST_SU2_F32, double>
-                                       : &k_sweep_su2<G, gfs::UPD_OR, gfs::ST_SU2_F32, float>;
-    if (upd == gfs::UPD_MICRO) return ctd ? &k_sweep_su2<G, gfs::UPD_MICRO, gfs::ST_SU2_F32, double>
-                                          : &k_sweep_su2<G, gfs::UPD_MICRO, gfs::ST_SU2_F32, float>;
-    if (!ctd) return nullptr;
-    if (upd == gfs::UPD_HEATBATH) return &k_sweep_su2<G, gfs::UPD_HEATBATH, gfs::ST_SU2_F32, double>;
-    if (upd == gfs::UPD_SR) return &k_sweep_su2<G, gfs::UPD_SR, gfs::ST_SU2_F32, double>;
-    return nullptr;
 }
 
-sweep_fn sweep_kernel_su2(int gauge, int upd, int st, int ctd, int W) {
-    if (W != 1) return nullptr;
-    if (gauge == gfs::LANDAU) return su2_variant<gfs::LANDAU>(upd, st, ctd);
-    if (gauge == gfs::COULOMB) return su2_variant<gfs::COULOMB>(upd, st, ctd);
-    return su2_variant<gfs::MAG>(upd, st, ctd);
+template <int G, int ST, int... I>
+std::array<sweep_fn, sizeof...(I)> su2_table(std::integer_sequence<int, I...>) {
+    return {{su2_entry<G, ST, I>()...}};
+}
+
+template <int G, int ST>
+sweep_fn su2_lookup(int upd, int ctd, int bi) {
+    static const std::array<sweep_fn, NSUB2> t = su2_table<G, ST>(std::make_integer_sequence<int, NSUB2>{});
+    return t[(bi * NCTD + ctd) * NUPD + upd];
+}
+
+template <int G>
+static sweep_fn su2_by_storage(int upd, int st, int ctd, int bi) {
+    if (st == gfs::ST_SU2_F64) return su2_lookup<G, gfs::ST_SU2_F64>(upd, ctd, bi);
+    if (st == gfs::ST_SU2_F32) return su2_lookup<G, gfs::ST_SU2_F32>(upd, ctd, bi);
+    return su2_lookup<G, gfs::ST_SU2_F32_SP>(upd, ctd, bi);
+}
+
+sweep_fn sweep_kernel_su2(int gauge, int upd, int st, int ctd, int W, int B, int nt) {
+    if (!su2_built(upd, st, ctd, W, B, nt)) return nullptr;
+    const int bi = block_index(B);
+    if (gauge == gfs::LANDAU) return su2_by_storage<gfs::LANDAU>(upd, st, ctd, bi);
+    if (gauge == gfs::COULOMB) return su2_by_storage<gfs::COULOMB>(upd, st, ctd, bi);
+    return su2_by_storage<gfs::MAG>(upd, st, ctd, bi);
 }
 
 static inline unsigned nblk_su2(int64_t n) { return (unsigned)((n + MBLOCK - 1) / MBLOCK); }

@@ -29,6 +29,9 @@ LANDAU, COULOMB, MAG = 0, 1, 2
 OR, MICRO, ANNEAL, SR, HEATBATH = 0, 1, 2, 3, 4
 F64_R18, F64_R12, MIXED_F32_R12, F32_R12 = 0, 1, 2, 3
 DL_REUNITARISE = 1
+KERNELS_FP32, KERNELS_FP64, KERNELS_HEATBATH = 0, 1, 2
+SHAPE_NONTEMPORAL, SHAPE_LINEAR_TILES = 1, 2
+KERNEL_TABLES = {"fp32": KERNELS_FP32, "fp64": KERNELS_FP64, "heatbath": KERNELS_HEATBATH}
 
 GAUGES = {"landau": LANDAU, "coulomb": COULOMB, "mag": MAG}
 UPDATES = {"or": OR, "micro": MICRO, "anneal": ANNEAL, "sr": SR, "heatbath": HEATBATH}
@@ -86,6 +89,10 @@ def load():
     L.gf_set_sweep_index.argtypes = [vp, i32, u64]
     L.gf_set_launch.argtypes = [vp, ci, ci]
     L.gf_autotune.argtypes = [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    L.gf_autotune_heatbath.argtypes = [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    L.gf_set_shape.argtypes = [vp, ci, ci, ci, ci]
+    L.gf_get_shape.argtypes = [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    L.gf_set_tune_cache.argtypes = [vp, ctypes.c_char_p]
     L.gf_set_timing.argtypes = [vp, ci]
     L.gf_kernel_time.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_int64), dp]
     L.gf_set_graph.argtypes = [vp, ci]
@@ -305,11 +312,35 @@ class GaugeFixer:
     def set_launch(self, waves_per_site=0, block=0):
         self._check(self.lib.gf_set_launch(self._h, int(waves_per_site), int(block)))
 
+    def set_shape(self, kernels, waves_per_site, block, flags=0):
+        """launch shape of one kernel table ("fp32", "fp64", "heatbath")"""
+        self._check(self.lib.gf_set_shape(self._h, _key(KERNEL_TABLES, kernels), int(waves_per_site), int(block),
+                                          int(flags)))
+
+    def get_shape(self, kernels):
+        """(waves_per_site, block, flags) of one kernel table"""
+        w, b, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.gf_get_shape(self._h, _key(KERNEL_TABLES, kernels), ctypes.byref(w), ctypes.byref(b),
+                                          ctypes.byref(f)))
+        return w.value, b.value, f.value
+
     def autotune(self, reps=3):
+        """tune the OR kernel tables in use; returns (waves_per_site, block)"""
         w = ctypes.c_int()
         b = ctypes.c_int()
         self._check(self.lib.gf_autotune(self._h, int(reps), ctypes.byref(w), ctypes.byref(b)))
         return w.value, b.value
+
+    def autotune_heatbath(self, reps=3):
+        """tune the heatbath kernel table; returns (waves_per_site, block)"""
+        w = ctypes.c_int()
+        b = ctypes.c_int()
+        self._check(self.lib.gf_autotune_heatbath(self._h, int(reps), ctypes.byref(w), ctypes.byref(b)))
+        return w.value, b.value
+
+    def set_tune_cache(self, path):
+        """file of persisted autotuning choices (None: off)"""
+        self._check(self.lib.gf_set_tune_cache(self._h, None if path is None else str(path).encode()))
 
     def set_timing(self, enable=True, every=1):
         """time every `every`-th half-sweep launch with HIP events (enable=False: off)"""

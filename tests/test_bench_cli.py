@@ -19,8 +19,10 @@ def test_traffic_only_for_the_profiled_kernel_sources(monkeypatch):
     digest = bench.kernel_digest()
     assert len(digest) == 16
     monkeypatch.setattr(bench, "COUNTER_DIGEST", digest)
-    assert bench.measured_traffic(1) == bench.COUNTER_TRAFFIC[1]
+    monkeypatch.setattr(bench, "COUNTER_TRAFFIC", {"1/256/0": 402902697})
+    assert bench.measured_traffic("1/256/0") == 402902697
+    assert bench.measured_traffic("2/256/0") is None
     monkeypatch.setattr(bench, "COUNTER_DIGEST", "0" * 16)
-    assert bench.measured_traffic(1) is None
+    assert bench.measured_traffic("1/256/0") is None
     monkeypatch.setattr(bench, "COUNTER_DIGEST", None)
-    assert bench.measured_traffic(1) is None
+    assert bench.measured_traffic("1/256/0") is None
