@@ -56,8 +56,13 @@ COUNTER_SOURCES = ("paper_1212_5221_amd/csrc/gf_sweep.hpp", "paper_1212_5221_amd
                    "paper_1212_5221_amd/csrc/gf_shared.hpp", "paper_1212_5221_amd/csrc/gf_variants.hpp",
                    "paper_1212_5221_amd/csrc/gf_sweep_table.hpp", "paper_1212_5221_amd/csrc/gf_sweep_inst.hip",
                    "paper_1212_5221_amd/build.py")
-COUNTER_DIGEST = None
-COUNTER_TRAFFIC = {}
+COUNTER_DIGEST = "2c4f82d41ffbb084"
+COUNTER_TRAFFIC = {"1/256/0": 402911686, "1/128/0": 402944657, "1/512/0": 402895302, "1/64/0": 403009987,
+                   "2/256/0": 402918853}
+# the same for the 48^4 lattice (non-temporal traffic, linear tile order;
+# profiles/k_sweep_landau_48x4_mixed_beyond_cache.md)
+COUNTER_TRAFFIC_48 = {"1/256/3": 2050516848, "1/128/3": 2052550865, "1/512/3": 2048604665, "1/64/3": 2057257839,
+                      "2/128/3": 2057228246}
 
 
 def kernel_digest():
@@ -69,10 +74,10 @@ def kernel_digest():
     return d.hexdigest()[:16]
 
 
-def measured_traffic(shape_key):
+def measured_traffic(shape_key, table=None):
     if COUNTER_DIGEST is None or kernel_digest() != COUNTER_DIGEST:
         return None
-    return COUNTER_TRAFFIC.get(shape_key)
+    return (COUNTER_TRAFFIC if table is None else table).get(shape_key)
 
 
 def fp64_policy():
@@ -219,6 +224,7 @@ def beyond_cache(gf, torch, I, L=48, sweeps=40):
     fx.set_overrelax(OMEGA)
     fx.autotune(reps=3)
     shape = fx.get_shape("fp32")
+    key = "%d/%d/%d" % shape
     fx.set_timing(True)
     fx.sweep("or", max_sweeps=sweeps, tol=0.0, check_every=CHECK)
     n, ms = fx.kernel_time("fp32")
@@ -228,7 +234,8 @@ def beyond_cache(gf, torch, I, L=48, sweeps=40):
     achieved = bpl / (ms * 1e-3) / 1e9
     torch.cuda.empty_cache()
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "lattice": list(dims),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(key, COUNTER_TRAFFIC_48) if L == 48 else None,
+            "lattice": list(dims),
             "link_bytes": 48 * 4 * V, "kernel": "k_sweep (half-sweep)",
             "shape": {"waves_per_site_group": shape[0], "block": shape[1],
                       "nontemporal": bool(shape[2] & gf.SHAPE_NONTEMPORAL),
@@ -645,6 +652,13 @@ def main():
                     help="only time the half-sweep of every gauge, storage and update on 32^4 (one JSON line each)")
     ap.add_argument("--profile-sweeps", type=int, default=0,
                     help="only run this many OR sweeps of the workload (for profiler counter runs)")
+    ap.add_argument("--stream-sizes", action="store_true",
+                    help="only time the streaming kernels (copy, non-temporal copy, read) over buffer sizes "
+                         "16 MiB .. 2 GiB (one JSON line each)")
+    ap.add_argument("--profile-lattice", type=int, default=32,
+                    help="lattice extent L (L^4) of --profile-sweeps (default 32)")
+    ap.add_argument("--profile-shapes", default="1/256/0",
+                    help="launch shapes W/B/flags of --profile-sweeps, comma-separated (default 1/256/0)")
     ap.add_argument("--profile-heatbath", type=int, default=0,
                     help="only run this many heatbath sweeps (T = 0.5) of the 32^4 workload in Landau and MAG gauge, "
                          "mixed storage (for profiler counter runs)")
@@ -670,6 +684,12 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}))
+        return
+    if args.stream_sizes:
+        for mb in (16, 32, 64, 128, 160, 200, 256, 320, 512, 1024, 2048):
+            c = copy_ceiling(gf, torch, mb << 20)
+            print(json.dumps({"MiB_read": mb, **{k: (round(v, 1) if isinstance(v, float) else v)
+                                                 for k, v in c.items()}}), flush=True)
         return
     if args.kernel_table:
         kernel_table(gf, I)
@@ -707,22 +727,28 @@ def main():
               flush=True)
         return
     if args.profile_sweeps:
-        # a fixed number of OR sweeps of seed 2001 in the benchmark's launch
-        # configuration (for profiler counter runs)
-        # configuration for every waves-per-site-group variant in turn (for
-        # profiler counter runs; the kernel names carry the variant)
-        fx = make_fixer(gf, "mixed")
-        bpl = BYTES_PER_SITE["mixed"] * int(np.prod(DIMS)) / 2
-        out = {"profile_sweeps": args.profile_sweeps, "kernel_digest": kernel_digest(), "bytes_per_launch": bpl}
-        for w in (1, 2, 4):
-            fx.set_launch(w)
-            fx.upload(0, I.smooth(DIMS, EPS, SEEDS[0]))
+        # a fixed number of OR sweeps of the seed-2001 configuration on an
+        # L^4 lattice (uploaded in slabs of 8 time-slices) with the FP32-update
+        # half-sweep in each given launch shape "W/B/flags" in turn (for
+        # profiler counter runs; the kernel names carry the shape)
+        L = args.profile_lattice
+        dims = (L, L, L, L)
+        fx = gf.GaugeFixer([dims], gauge="landau", storage="mixed", reunit_every=REUNIT)
+        fx.set_overrelax(OMEGA)
+        bpl = BYTES_PER_SITE["mixed"] * L ** 4 / 2
+        out = {"profile_sweeps": args.profile_sweeps, "lattice": list(dims), "kernel_digest": kernel_digest(),
+               "bytes_per_launch": bpl}
+        for key in args.profile_shapes.split(","):
+            w, b, f = (int(x) for x in key.split("/"))
+            fx.set_shape("fp32", w, b, f)
+            for t0 in range(0, L, 8):
+                fx.upload(0, I.smooth(dims, EPS, SEEDS[0], t0=t0, nt=min(8, L - t0)), t0=t0, nt=min(8, L - t0))
             fx.set_timing(True)
             fx.sweep("or", max_sweeps=args.profile_sweeps, tol=0.0, check_every=args.profile_sweeps)
             n, ms = fx.kernel_time("fp32")
             fx.set_timing(False)
-            out["waves_%d" % w] = {"launches": n, "mean_launch_ms": ms,
-                                   "achieved_GBs": bpl / (ms * 1e-3) / 1e9 if ms > 0 else None}
+            out[key] = {"launches": n, "mean_launch_ms": ms,
+                        "achieved_GBs": bpl / (ms * 1e-3) / 1e9 if ms > 0 else None}
         fx.close()
         print(json.dumps(out))
         return

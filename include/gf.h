@@ -128,7 +128,10 @@ int gf_set_group(gf_handle h, int nc);
    measured theta of a unit is below `fp64_tail_theta` (0 = never, >= 1e300 =
    always; mixed storage only).  Mixed storage always applies the product G of a site's three
    subgroup elements to its links in FP64, after reprojecting a G built in
-   FP32 to SU(3), and rounds the result to FP32.  12-real storages store a
+   FP32 to SU(3), and rounds the result to FP32.  Heatbath sweeps on FP32
+   storage (SU(3)) compute the local algebra in FP32 and draw the sample in
+   FP64 (FP64 throughout with fp64_tail_theta >= 1e300); stochastic
+   relaxation computes in FP64.  12-real storages store a
    left-multiplied link after one first-order renormalisation of its two rows
    (without it, rebuilding the third row lets their norm defect grow under
    large updates).  With FP32 storage (GF_MIXED_F32_R12, GF_F32_R12) and

@@ -307,6 +307,14 @@ gfs::InstDev inst_dev(const InstHost &I) {
     return d;
 }
 
+// compute precision of the heatbath kernels: FP32 on FP32 storage (SU(3);
+// the local algebra in FP32 as for overrelaxation, the sample drawn in FP64,
+// G applied in FP64), unless the FP64 update is requested throughout
+int heatbath_ctd(const gf_ctx *h) {
+    const bool f32 = h->storage == GF_MIXED_F32_R12 || h->storage == GF_F32_R12;
+    return (h->nc == 3 && f32 && h->tail_theta < 1e300) ? 0 : 1;
+}
+
 // sweep tile table `tab` (0 FP32 update, 1 FP64 update, 2 heatbath) for the
 // launch shape `sh`: tiles of B / W sites
 int build_tiles(gf_ctx *h, int tab, const Shape &sh) {
@@ -335,8 +343,8 @@ int build_tiles(gf_ctx *h, int tab, const Shape &sh) {
 gfl::sweep_fn table_kernel(const gf_ctx *h, int tab, const Shape &sh) {
     const int st = st_code(h);
     const int upd = (tab == 2) ? gfs::UPD_HEATBATH : gfs::UPD_OR;
-    const int ctd = (tab == 0) ? 0 : 1;
-    const int kst = (h->storage == GF_F32_R12 && ctd == 0)
+    const int ctd = (tab == 2) ? heatbath_ctd(h) : (tab == 0) ? 0 : 1;
+    const int kst = (h->storage == GF_F32_R12 && tab == 0)
                         ? (h->nc == 2 ? (int)gfs::ST_SU2_F32_SP : (int)gfs::ST_F32R12_SP)
                         : st;
     if (tab == 1 && !gfl::sweep_kernel(h->gauge, gfs::UPD_SR, st, 1, sh.W, sh.B, 0)) return nullptr;
@@ -481,7 +489,7 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
     if (h->force_ctd >= 0) {
         launches[nl++] = {h->force_ctd, -1, h->force_ctd};
     } else if (upd == gfs::UPD_HEATBATH) {
-        launches[nl++] = {1, -1, 2};
+        launches[nl++] = {heatbath_ctd(h), -1, 2};
     } else if (single && !hb) {
         launches[nl++] = {0, -1, 0};
     } else if (!mixed || hb) {
@@ -502,7 +510,10 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
     for (int k = 0; k < nl; ++k) {
         const int ctd = launches[k].ctd, tab = launches[k].tab;
         // single precision: the FP32-update kernels that also apply G in FP32
-        const int kst = (single && ctd == 0) ? (h->nc == 2 ? (int)gfs::ST_SU2_F32_SP : (int)gfs::ST_F32R12_SP) : st;
+        // (the heatbath applies G in FP64 on both FP32 storages)
+        const int kst = (single && ctd == 0 && upd != gfs::UPD_HEATBATH)
+                            ? (h->nc == 2 ? (int)gfs::ST_SU2_F32_SP : (int)gfs::ST_F32R12_SP)
+                            : st;
         const Shape &sh = h->shape[tab];
         // the random updates have cached variants only
         gfl::sweep_fn fn = gfl::sweep_kernel(h->gauge, upd, kst, ctd, sh.W, sh.B, gfl::is_random(upd) ? 0 : sh.nt);

@@ -545,10 +545,20 @@ __global__ __launch_bounds__(BLK) void k_sweep(gfs::SweepArgs a) {
     // ---- Step 2: apply G to this wave's links and store.
     // The empty asm makes the stored rows opaque, so the compiler rebuilds
     // the third rows here instead of keeping all expanded links live.
+    // Landau/Coulomb heatbath: K holds all the sampler needs, so the links
+    // are read again for Step 2, one at a time, instead of being held
+    // through the sampling; their registers are free while the sampler's
+    // long dependent chains run, and more waves fit on a SIMD to hide them.
+    // The second read mostly hits the caches.
+    constexpr bool RELOAD = (UPD == gfs::UPD_HEATBATH) && (GAUGE != gfs::MAG);
+    if constexpr (RELOAD) {
+        asm volatile("" ::: "memory");
+    } else {
 #pragma unroll
-    for (int q = 0; q < LPW; ++q)
+        for (int q = 0; q < LPW; ++q)
 #pragma unroll
-        for (int c = 0; c < SD::NR; ++c) asm volatile("" : "+v"(r[q][c]));
+            for (int c = 0; c < SD::NR; ++c) asm volatile("" : "+v"(r[q][c]));
+    }
     // FP32 storage: G is applied in FP64, and a G built in FP32 is first
     // reprojected to SU(3) in FP64.  An exactly unitary G keeps the links on
     // their gauge orbit, so the only loss is the rounding of the stored links.
@@ -565,6 +575,11 @@ __global__ __launch_bounds__(BLK) void k_sweep(gfs::SweepArgs a) {
         const bool fw = l < NDIR;
         const int mu = MU0 + (fw ? l : l - NDIR);
         M3<AT> m, o;
+        if constexpr (RELOAD) {
+            SD::template load<NT != 0>(plane_ptr<ST>(a.ws, I, fw ? p : 1 - p, mu), I.Vh, lh[q], r[q]);
+#pragma unroll
+            for (int c = 0; c < SD::NR; ++c) asm volatile("" : "+v"(r[q][c]));
+        }
         expand<ST, AT>(r[q], m);
         if (fw) {
             apply_left(Ga, m, o, SD::ROWS);

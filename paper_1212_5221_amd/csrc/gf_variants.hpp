@@ -31,8 +31,9 @@ constexpr int sub_index(int upd, int ctd, int wi, int bi, int nt) {
 constexpr bool is_random(int upd) { return upd == gfs::UPD_HEATBATH || upd == gfs::UPD_SR; }
 
 // SU(3):
-//  - FP64 storage updates in FP64; mixed FP32 storage in FP32 or FP64 (the
-//    random updates, heatbath and stochastic relaxation, in FP64 only);
+//  - FP64 storage updates in FP64; mixed FP32 storage in FP32 or FP64
+//    (stochastic relaxation in FP64 only; the heatbath's local algebra in
+//    either, its sample always in FP64);
 //    single precision: overrelaxation and microcanonical steps in FP32;
 //  - W divides the site's links (8, Coulomb 6) and a block holds at least
 //    one group of 64 sites (B >= 64 W);
@@ -47,7 +48,7 @@ constexpr bool su3_built(int gauge, int upd, int st, int ctd, int W, int B, int 
     if (nt && is_random(upd)) return false;
     if (B == 512 && ctd == 1 && (W == 1 || is_random(upd))) return false;
     if (st == gfs::ST_F64R18 || st == gfs::ST_F64R12) return ctd == 1;
-    if (st == gfs::ST_F32R12) return ctd == 1 || !is_random(upd);
+    if (st == gfs::ST_F32R12) return ctd == 1 || upd != gfs::UPD_SR;
     if (st == gfs::ST_F32R12_SP) return ctd == 0 && !is_random(upd);
     return false;
 }

@@ -314,12 +314,19 @@ def test_checkpoint_files_resume_bit_identically(storage, tmp_path):
 @pytest.mark.parametrize("update", ["heatbath", "sr"])
 def test_mixed_random_halfsweeps_match_oracle_from_the_stored_state(gauge, waves, update):
     # Mixed storage cannot follow the FP64 chain, so each half-sweep of the
-    # heatbath and stochastic-relaxation kernels on FP32-12 storage (update
-    # computed in FP64) is recomputed by the oracle from the state the GPU
-    # stored before it (same seed, temperature and sweep index).  Both sides
-    # then start from the same links; the GPU's result differs only by the
-    # FP32 rounding of the stored rows and the first-order renormalisation of
-    # the forward links before it, each a few ulp(1) = 6e-8: bound 1e-6.
+    # heatbath and stochastic-relaxation kernels on FP32-12 storage is
+    # recomputed by the oracle from the state the GPU stored before it (same
+    # seed, temperature and sweep index).  Stochastic relaxation computes the
+    # update in FP64: the result differs only by the FP32 rounding of the
+    # stored rows and the first-order renormalisation of the forward links
+    # before it, each a few ulp(1) = 6e-8: bound 1e-6.  The heatbath computes
+    # its local algebra (K, the MAG coefficients, the subgroup products) in
+    # FP32 like overrelaxation and draws the sample in FP64 from it: the
+    # sample is a smooth function of the FP32 direction and strength, with
+    # the errors of a few ulp(8) that bound the FP32 overrelaxation step:
+    # 3e-5.  (A rejection decision within ~1e-7 of its boundary could flip;
+    # at these temperatures the Kennedy-Pendleton branch, where that
+    # probability is ~1e-9 per decision, draws almost all samples.)
     dims = (4, 4, 6, 4)
     say("mixed", update, "half-sweeps from the stored state", gauge, "waves", waves)
     fx = fixer([dims], gauge, "mixed", waves=waves)
@@ -335,5 +342,5 @@ def test_mixed_random_halfsweeps_match_oracle_from_the_stored_state(gauge, waves
             out = fx.download(0)
             O.halfsweep(S, dims, gauge, update, parity, omega=1.0, T=0.8, p_sr=0.5, seed=41, instance=0, sweep=k)
             err = np.max(np.abs(out - S))
-            assert err < 1e-6, (k, parity, err)
+            assert err < (3e-5 if update == "heatbath" else 1e-6), (k, parity, err)
     fx.close()

@@ -12,7 +12,8 @@ of 512), compared with the oracle to the bounds of test_gpu_parity, and --
 since block size, cache policy and tile order do not touch the arithmetic of
 a site -- bit for bit with the other shapes of the same W.  Random updates
 on FP32 storage are compared half-sweep by half-sweep with the oracle run
-from the state the GPU stored (1e-6, as in test_gpu_anneal).
+from the state the GPU stored (1e-6; the heatbath on mixed storage, whose
+local algebra is FP32, 3e-5; as in test_gpu_anneal).
 
 The autotuner: the bound state (links, sweep indices, stop flags) is the
 same before and after tuning, and a tuning cache hands a second handle of
@@ -100,7 +101,9 @@ def test_every_shape_matches_oracle(gauge, storage):
                     O.halfsweep(S, DIMS, gauge, update, parity, omega=1.7, T=0.7, p_sr=0.5, seed=77, instance=0,
                                 sweep=0, G=O.identity_field(int(np.prod(DIMS))) if gauge == "coulomb" else None)
                     err = float(np.max(np.abs(out - S)))
-                    assert err < 1e-6, (gauge, storage, update, w, b, f, parity, err)
+                    # the heatbath on mixed storage: FP32 local algebra (test_gpu_anneal)
+                    tol = 3e-5 if (update == "heatbath" and storage == "mixed") else 1e-6
+                    assert err < tol, (gauge, storage, update, w, b, f, parity, err)
             out = fx.download(0)
             if not stepwise:
                 err = float(np.max(np.abs(out - ref)))
