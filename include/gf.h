@@ -351,8 +351,9 @@ int gf_set_graph(gf_handle h, int enable);
    memory traffic one half-sweep is compared with.  kind GF_STREAM_COPY*:
    copy `bytes` from `src` to `dst` (device pointers, 16-byte aligned, bytes
    a multiple of 16), 16-byte loads and stores, optionally non-temporal;
-   GF_STREAM_READ: read `bytes` of `src` and write one float per 4 KiB block
-   to `dst` (gf_stream_blocks gives the count; dst must hold that many).
+   GF_STREAM_READ: read `bytes` of `src` and write the sum of each 16 KiB
+   block as one float to `dst` (gf_stream_blocks gives the count; dst must
+   hold that many).
    Enqueued on `hip_stream`; returns without waiting.  GF_E_INVALID for bad
    arguments, GF_E_HIP if the launch fails. */
 #define GF_STREAM_COPY 0
