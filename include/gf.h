@@ -87,9 +87,9 @@ int gf_create(gf_handle *out, int hip_device, void *hip_stream);
 /* Destroy a handle.  Frees host state only; the workspace stays the caller's. */
 void gf_destroy(gf_handle h);
 
-/* Message of the last non-OK status on `h` (or of the last failed gf_create
-   or gf_measure_noalloc when h is NULL); valid until the next call on that
-   handle. */
+/* Message of the last non-OK status on `h` (or, when h is NULL, of the
+   calling thread's last failed gf_create or gf_measure_noalloc); valid until
+   the next call on that handle (that thread). */
 const char *gf_last_error(gf_handle h);
 
 /* Add a lattice instance of extents dims = {Nt, Nx, Ny, Nz}.  Every extent
@@ -296,7 +296,8 @@ int gf_get_shape(gf_handle h, int kernels, int *waves_per_site, int *block, int 
    them (gf_set_cache_budget); the smallest median wins.  The trial sweeps
    run on the bound links; the links, the Coulomb accumulators, the sweep
    indices and counts and the stop flags are saved to host memory before
-   and written back after, so the caller's state is unchanged.
+   and written back after, so the caller's state is unchanged (GF_E_NOMEM
+   if the host memory for that copy cannot be allocated).
    *waves_per_site and *block (may be NULL) receive the choice (of the
    precision doing most sweeps).  With a tuning cache (gf_set_tune_cache)
    a table whose key is in the cache takes the stored shape without timing,

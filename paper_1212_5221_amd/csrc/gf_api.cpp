@@ -12,6 +12,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <new>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -138,7 +139,8 @@ struct gf_ctx {
 
 namespace {
 
-std::string g_create_error;
+// message of the last failure without a handle (gf_create, gf_measure_noalloc), per host thread
+thread_local std::string g_create_error;
 
 int fail(gf_ctx *h, int code, const char *fmt, ...) {
     char buf[512];
@@ -1402,8 +1404,13 @@ struct Snapshot {
 };
 
 int save_state(gf_ctx *h, Snapshot &sn) {
-    sn.lat.resize(h->off_inst);
-    sn.book.resize(h->off_status + 256 - h->off_res);
+    try {
+        sn.lat.resize(h->off_inst);
+        sn.book.resize(h->off_status + 256 - h->off_res);
+    } catch (const std::bad_alloc &) {
+        return fail(h, GF_E_NOMEM, "autotuning: no host memory for the %zu bytes of saved state",
+                    (size_t)h->off_inst);
+    }
     HIPCHK(h, hipMemcpyAsync(sn.lat.data(), h->ws, sn.lat.size(), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemcpyAsync(sn.book.data(), h->ws + h->off_res, sn.book.size(), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
