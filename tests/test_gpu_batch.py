@@ -62,7 +62,13 @@ def test_c5_gribov_batch_full_size():
             k += 1
     fx.set_overrelax(1.7)
     fx.autotune(reps=1)
-    # the autotuner runs real sweeps: start the fix from the inputs again
+    # block size, cache policy and tile order leave the arithmetic of a site
+    # unchanged, the number of wavefronts per site group changes the FP32
+    # summation order of K; one wavefront keeps the run the same from call to
+    # call (every W is compared with the oracle in test_gpu_shapes), so the
+    # Gribov copy it reaches does not depend on the timing noise of tuning
+    w, b, f = fx.get_shape("fp32")
+    fx.set_shape("fp32", 1, b, f)
     k = 0
     for li, d in enumerate(shapes):
         for c in range(ncopy):
