@@ -429,12 +429,26 @@ __device__ __forceinline__ int64_t natural_index(const gfs::InstDev &I, const Si
 // ---------------------------------------------------------------- Philox4x64-10
 // Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
 // (SC'11): 10 rounds of the 4x64 bijection with a Weyl-sequence key schedule.
+// The 128-bit product a b as (lo, hi) from four 32 x 32 -> 64 products
+// (schoolbook; each partial sum stays below 2^64), so that low and high
+// halves share their partial products (one v_mad_u64_u32 each).
+__device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi) {
+    const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32), bl = (uint32_t)b, bh = (uint32_t)(b >> 32);
+    const uint64_t p0 = (uint64_t)al * bl;
+    const uint64_t p1 = (uint64_t)al * bh + (p0 >> 32);
+    const uint64_t p2 = (uint64_t)ah * bl + (uint32_t)p1;
+    const uint64_t p3 = (uint64_t)ah * bh + (p1 >> 32) + (p2 >> 32);
+    lo = (p2 << 32) | (uint32_t)p0;
+    hi = p3;
+}
+
 __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
     const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
-        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        uint64_t lo0, hi0, lo1, hi1;
+        mulhilo64(M0, c[0], lo0, hi0);
+        mulhilo64(M1, c[2], lo1, hi1);
         const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
         c[0] = n0;
         c[1] = lo1;
