@@ -56,13 +56,13 @@ COUNTER_SOURCES = ("paper_1212_5221_amd/csrc/gf_sweep.hpp", "paper_1212_5221_amd
                    "paper_1212_5221_amd/csrc/gf_shared.hpp", "paper_1212_5221_amd/csrc/gf_variants.hpp",
                    "paper_1212_5221_amd/csrc/gf_sweep_table.hpp", "paper_1212_5221_amd/csrc/gf_sweep_inst.hip",
                    "paper_1212_5221_amd/build.py")
-COUNTER_DIGEST = "2c4f82d41ffbb084"
-COUNTER_TRAFFIC = {"1/256/0": 402911686, "1/128/0": 402944657, "1/512/0": 402895302, "1/64/0": 403009987,
-                   "2/256/0": 402918853}
+COUNTER_DIGEST = "079e1199447c65ec"
+COUNTER_TRAFFIC = {"1/256/0": 402911937, "1/128/0": 402931194, "1/512/0": 402895355, "1/64/0": 403010040,
+                   "2/256/0": 402935795}
 # the same for the 48^4 lattice (non-temporal traffic, linear tile order;
 # profiles/k_sweep_landau_48x4_mixed_beyond_cache.md)
-COUNTER_TRAFFIC_48 = {"1/256/3": 2050516848, "1/128/3": 2052550865, "1/512/3": 2048604665, "1/64/3": 2057257839,
-                      "2/128/3": 2057228246}
+COUNTER_TRAFFIC_48 = {"1/256/3": 2050320999, "1/128/3": 2052505301, "1/512/3": 2048528273, "1/64/3": 2057269007,
+                      "2/128/3": 2057208470}
 
 
 def kernel_digest():
