@@ -222,7 +222,7 @@ def beyond_cache(gf, torch, I, L=48, sweeps=40):
         fx.upload(0, slab, t0=t0, nt=8)
         del slab
     fx.set_overrelax(OMEGA)
-    fx.autotune(reps=3)
+    fx.autotune(reps=8)  # the best shapes lie within 2% of each other here
     shape = fx.get_shape("fp32")
     key = "%d/%d/%d" % shape
     fx.set_timing(True)
@@ -568,6 +568,38 @@ def landau_temperature_scan(gf, torch, I, nsteps=3000, T0=4.0, T1=1e-4, nseg=10)
                       "total_s": round(t_all, 3)}), flush=True)
 
 
+def lattice_scan(gf, torch, I, nsweeps=20):
+    """Half-sweep time against the lattice size (the paper's performance-vs-
+    volume study): Landau OR on L^4 for L = 16 ... 56, FP32-12 mixed and
+    FP64-12, smooth input (eps 0.5, seed 2001) uploaded in slabs of 8
+    time-slices, autotuned, then nsweeps sweeps timed with kernel events; one
+    JSON line per lattice and storage."""
+    link = {"mixed": 48, "f64r12": 96}
+    for L in (16, 24, 32, 40, 48, 56):
+        dims = (L, L, L, L)
+        V = L ** 4
+        for storage in ("mixed", "f64r12"):
+            fx = gf.GaugeFixer([dims], gauge="landau", storage=storage, reunit_every=0)
+            for t0 in range(0, L, 8):
+                fx.upload(0, I.smooth(dims, EPS, SEEDS[0], t0=t0, nt=min(8, L - t0)), t0=t0, nt=min(8, L - t0))
+            fx.set_overrelax(OMEGA)
+            fx.autotune(reps=3)
+            table = "fp32" if storage == "mixed" else "fp64"
+            shape = fx.get_shape(table)
+            fx.set_timing(True)
+            fx.sweep("or", max_sweeps=nsweeps, tol=0.0, check_every=nsweeps)
+            n, ms = fx.kernel_time(table)
+            fx.set_timing(False)
+            fx.close()
+            bps = 16 * link[storage]
+            gbs = bps * V / 2 / (ms * 1e-3) / 1e9
+            print(json.dumps({"lattice": list(dims), "storage": storage, "link_MB": round(4 * V * link[storage] / 1e6, 1),
+                              "shape": "%d/%d/%d" % shape, "mean_launch_ms": round(ms, 5),
+                              "site_updates_per_s": V / 2 / (ms * 1e-3), "GBs": round(gbs, 1),
+                              "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}), flush=True)
+            torch.cuda.empty_cache()
+
+
 def kernel_table(gf, I, nsweeps=20):
     """Half-sweep launch time and effective bandwidth of every gauge x
     storage x update on a 32^4 lattice (Coulomb: 32 time-slices of 32^3),
@@ -652,6 +684,9 @@ def main():
                     help="only time the half-sweep of every gauge, storage and update on 32^4 (one JSON line each)")
     ap.add_argument("--profile-sweeps", type=int, default=0,
                     help="only run this many OR sweeps of the workload (for profiler counter runs)")
+    ap.add_argument("--lattice-scan", action="store_true",
+                    help="only time the Landau OR half-sweep on L^4, L = 16 ... 56, mixed and FP64-12 (one JSON "
+                         "line each)")
     ap.add_argument("--stream-sizes", action="store_true",
                     help="only time the streaming kernels (copy, non-temporal copy, read) over buffer sizes "
                          "16 MiB .. 2 GiB (one JSON line each)")
@@ -684,6 +719,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}))
+        return
+    if args.lattice_scan:
+        lattice_scan(gf, torch, I)
         return
     if args.stream_sizes:
         for mb in (16, 32, 64, 128, 160, 200, 256, 320, 512, 1024, 2048):
