@@ -290,10 +290,12 @@ int gf_get_shape(gf_handle h, int kernels, int *waves_per_site, int *block, int 
    size by measurement).  gf_autotune times every shape of the tables the
    OR sweeps of the bound configuration use (FP32 and/or FP64 update) and
    keeps the fastest; gf_autotune_heatbath does the same for the heatbath
-   table at the temperature of gf_set_temperature.  `reps` rounds visit
-   every shape in turn; a visit runs one untimed sweep and then times 3
-   back-to-back sweeps between two events, group by group as gf_sweep runs
-   them (gf_set_cache_budget); the smallest median wins.  The trial sweeps
+   table at the temperature of gf_set_temperature.  A visit to a shape
+   runs one untimed sweep and then times n back-to-back sweeps between two
+   events, group by group as gf_sweep runs them (gf_set_cache_budget).
+   Screening: `reps` rounds visit every shape in turn (n = 3); the 4 shapes
+   with the smallest medians then get max(reps, 3) rounds of visits with
+   n = 12, and the smallest median of those wins.  The trial sweeps
    run on the bound links; the links, the Coulomb accumulators, the sweep
    indices and counts and the stop flags are saved to host memory before
    and written back after, so the caller's state is unchanged (GF_E_NOMEM

@@ -1428,43 +1428,86 @@ int restore_state(gf_ctx *h, const Snapshot &sn) {
     return GF_OK;
 }
 
-// Time every shape of table `tab` with update `upd` and keep the fastest.
-// Rounds interleave the shapes (drifts of clock or temperature hit all of
-// them alike).  A visit switches the shape, runs one untimed sweep, then
-// times kSweeps back-to-back sweeps between two events, group by group as
-// gf_sweep runs them, so the figure is the sweep throughput including launch
-// gaps.  The smallest median wins.  All units are active during the trial.
+// One visit of shape `sh`: switch to it, run one untimed sweep, then time
+// `sweeps` back-to-back sweeps between two events, group by group as
+// gf_sweep runs them (the figure includes launch gaps); ms per sweep.
+int visit_shape(gf_ctx *h, int tab, int upd, const Shape &sh, int sweeps, hipEvent_t e0, hipEvent_t e1,
+                float *ms_per_sweep) {
+    int rc = build_tiles(h, tab, sh);
+    if (rc == GF_OK) rc = enqueue_chunk(h, upd, 1, 0, false);
+    if (rc == GF_OK) rc = count_chunk(h, 1);
+    if (rc) return rc;
+    HIPCHK(h, hipEventRecord(e0, h->cur));
+    rc = enqueue_chunk(h, upd, sweeps, 0, false);
+    if (rc == GF_OK) rc = count_chunk(h, sweeps);
+    if (rc) return rc;
+    HIPCHK(h, hipEventRecord(e1, h->cur));
+    HIPCHK(h, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+    *ms_per_sweep = ms / sweeps;
+    return GF_OK;
+}
+
+float median_of(std::vector<float> t) {
+    std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+    return t[t.size() / 2];
+}
+
+// Time every shape of table `tab` with update `upd` and keep the fastest, in
+// two stages, after a warm-up: untimed sweeps for about 20 ms, since the
+// first milliseconds of work after an idle GPU (the host copy of the saved
+// state just before) run at lower clocks and would count against the shapes
+// visited first.  Screening: `reps` rounds of a short visit (3 timed sweeps) to
+// every shape.  Final: the kFinal shapes with the smallest screening medians
+// get max(reps, 3) rounds of long visits (12 timed sweeps); the smallest
+// median of those wins.  Shapes of large lattices lie within a few per cent
+// of each other and some of them vary more from visit to visit than that, so
+// a short screening alone can crown one whose lucky visits it saw.  Rounds
+// interleave the shapes (drifts of clock or temperature hit all of them
+// alike).  All units are active during the trial.
 int time_shapes(gf_ctx *h, int tab, int upd, int reps, hipEvent_t e0, hipEvent_t e1, Shape *best) {
-    constexpr int kSweeps = 3;
+    constexpr int kScreen = 3, kLong = 12, kFinal = 4;
     const std::vector<Shape> cand = table_shapes(h, tab);
     if (cand.empty()) return fail(h, GF_E_INVALID, "kernel table %d has no variant", tab);
-    std::vector<std::vector<float>> times(cand.size());
     HIPCHK(h, gfl::fill_i32(wsp<int32_t>(h, h->off_active), 1, h->nunits, h->stream));
     h->n_active = h->nunits;
+    {
+        float ms = 0.f;
+        int rc = visit_shape(h, tab, upd, cand[0], 1, e0, e1, &ms);
+        const int nwarm = std::max(1, std::min(256, (int)std::ceil(20.0f / std::max(ms, 1e-3f))));
+        if (rc == GF_OK) rc = enqueue_chunk(h, upd, nwarm, 0, false);
+        if (rc == GF_OK) rc = count_chunk(h, nwarm);
+        if (rc) return rc;
+    }
+    std::vector<std::vector<float>> times(cand.size());
     for (int r = 0; r < reps; ++r)
         for (size_t k = 0; k < cand.size(); ++k) {
-            int rc = build_tiles(h, tab, cand[k]);
-            if (rc == GF_OK) rc = enqueue_chunk(h, upd, 1, 0, false);
-            if (rc == GF_OK) rc = count_chunk(h, 1);
-            if (rc) return rc;
-            HIPCHK(h, hipEventRecord(e0, h->cur));
-            rc = enqueue_chunk(h, upd, kSweeps, 0, false);
-            if (rc == GF_OK) rc = count_chunk(h, kSweeps);
-            if (rc) return rc;
-            HIPCHK(h, hipEventRecord(e1, h->cur));
-            HIPCHK(h, hipEventSynchronize(e1));
             float ms = 0.f;
-            HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
-            times[k].push_back(ms / kSweeps);
+            const int rc = visit_shape(h, tab, upd, cand[k], kScreen, e0, e1, &ms);
+            if (rc) return rc;
+            times[k].push_back(ms);
         }
-    double bt = 1e300;
-    for (size_t k = 0; k < cand.size(); ++k) {
-        std::vector<float> &t = times[k];
-        std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
-        const double med = t[t.size() / 2];
+    std::vector<std::pair<float, size_t>> order;
+    for (size_t k = 0; k < cand.size(); ++k) order.push_back({median_of(times[k]), k});
+    std::sort(order.begin(), order.end());
+    order.resize(std::min(order.size(), (size_t)kFinal));
+    *best = cand[order[0].second];
+    if (order.size() == 1) return GF_OK;
+    std::vector<std::vector<float>> fin(order.size());
+    for (int r = 0; r < std::max(reps, 3); ++r)
+        for (size_t i = 0; i < order.size(); ++i) {
+            float ms = 0.f;
+            const int rc = visit_shape(h, tab, upd, cand[order[i].second], kLong, e0, e1, &ms);
+            if (rc) return rc;
+            fin[i].push_back(ms);
+        }
+    float bt = 3.4e38f;
+    for (size_t i = 0; i < order.size(); ++i) {
+        const float med = median_of(fin[i]);
         if (med < bt) {
             bt = med;
-            *best = cand[k];
+            *best = cand[order[i].second];
         }
     }
     return GF_OK;
