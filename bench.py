@@ -192,28 +192,30 @@ def warm_up(fx, upd, ms=30.0):
 
 def copy_ceiling(gf, torch, nbytes, reps=20):
     """The streaming kernels of the library (gf_stream: 16-byte loads and
-    stores) reading and writing nbytes each (the bytes one half-sweep reads
-    and writes), cached and with non-temporal loads and stores, and reading
-    only; median of reps back-to-back passes each, as GB/s of bytes moved."""
+    stores) over nbytes, the bytes one half-sweep reads and writes: a copy
+    into a second buffer and an in-place pass (each 16 bytes read and written
+    back, as the half-sweep updates its links in place), each cached and
+    non-temporal, and a read-only pass.  Each kind: 3 untimed passes, then
+    `reps` passes back to back between two events (as the half-sweeps of a
+    chunk run); GB/s of bytes moved (read + written; read only for read)."""
     nbytes = nbytes // 16 * 16
     x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
     y = torch.empty_like(x)
     sink = torch.empty(gf.stream_blocks(nbytes), dtype=torch.float32, device="cuda:0")
-    out = {"bytes_read": nbytes, "kernel": "gf_stream (16-byte loads and stores)"}
-    for kind in ("copy", "copy_nt", "read"):
-        dst, moved = (sink, nbytes) if kind == "read" else (y, 2 * nbytes)
+    out = {"bytes_read": nbytes, "kernel": "gf_stream (16-byte loads and stores)", "passes": reps}
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for name, kind, dst, moved in (("copy", "copy", y, 2 * nbytes), ("copy_nt", "copy_nt", y, 2 * nbytes),
+                                   ("inplace", "copy", x, 2 * nbytes), ("inplace_nt", "copy_nt", x, 2 * nbytes),
+                                   ("read", "read", sink, nbytes)):
         for _ in range(3):
             gf.stream(kind, dst, x, nbytes)
-        ts = []
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(reps):
-            e0.record()
             gf.stream(kind, dst, x, nbytes)
-            e1.record()
-            e1.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        out[kind + "_GBs"] = moved / (float(np.median(ts)) * 1e-3) / 1e9
+        e1.record()
+        e1.synchronize()
+        out[name + "_GBs"] = moved * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del x, y, sink
     torch.cuda.empty_cache()
     return out
@@ -940,7 +942,8 @@ def main():
                      "mean_launch_ms": mean_ms, "launches": launches, "timed_chunks_every": TIME_EVERY,
                      "fp64_tail_launches": launches64, "fp64_tail_mean_ms": mean_ms64,
                      "copy_ceiling": ceiling,
-                     "note": "the 201 MB of links stay partly in the 256 MB Infinity Cache between half-sweeps; "
+                     "note": "the 201 MB of links stay partly in the 256 MB Infinity Cache between half-sweeps "
+                             "(compare copy_ceiling.inplace_GBs, an in-place streaming pass over the same bytes); "
                              "traffic counts L2-to-fabric bytes (FETCH_SIZE, WRITE_SIZE), cache hits included"},
         "roofline_beyond_cache": big,
         "cpu_baseline": cpu,

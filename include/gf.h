@@ -354,6 +354,8 @@ int gf_set_graph(gf_handle h, int enable);
    memory traffic one half-sweep is compared with.  kind GF_STREAM_COPY*:
    copy `bytes` from `src` to `dst` (device pointers, 16-byte aligned, bytes
    a multiple of 16), 16-byte loads and stores, optionally non-temporal;
+   dst == src is allowed and makes an in-place pass (every 16 bytes read and
+   written back, the traffic of an in-place update; other overlaps are not);
    GF_STREAM_READ: read `bytes` of `src` and write the sum of each 16 KiB
    block as one float to `dst` (gf_stream_blocks gives the count; dst must
    hold that many).

@@ -1,5 +1,6 @@
 """The streaming-ceiling kernels (gf_stream): every copy variant copies
-exactly, the read pass sums what it reads, and bad arguments are refused.
+exactly, an in-place pass (dst = src) leaves the data as it was, the read
+pass sums what it reads, and bad arguments are refused.
 Sizes include a ragged tail (not a multiple of one block's 16 KiB)."""
 import numpy as np
 import pytest
@@ -17,6 +18,19 @@ def test_copy_is_exact(kind):
     gf.stream(kind, y, x, n * 4)
     torch.cuda.synchronize()
     assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("kind", ["copy", "copy_nt"])
+def test_in_place_pass_keeps_the_data(kind):
+    import torch
+    from paper_1212_5221_amd import gf
+    n = (1 << 20) + 12
+    x = torch.randn(n, dtype=torch.float32, device="cuda:0")
+    ref = x.clone()
+    for _ in range(3):
+        gf.stream(kind, x, x, n * 4)
+    torch.cuda.synchronize()
+    assert torch.equal(x, ref)
 
 
 def test_read_sums_blocks():
