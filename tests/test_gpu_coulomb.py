@@ -6,8 +6,9 @@ Checked on sampled time-slices {0, 85, 170, 255}: one half-sweep recomputed
 site by site by the oracle from the same FP32-rounded input slice (the
 update of a time-slice depends on that slice only), and after the full fix
 the oracle's per-slice F_t and theta_t of the downloaded slice, after a
-bounded chunk of 2000 sweeps of all slices.  The full fix (100k sweeps)
-runs only with GF_LONG_TESTS=1.
+bounded chunk of 2000 sweeps of all slices.  The complete fix (every
+time-slice below 1e-12, about 150k sweeps and 13 minutes) runs only with
+GF_LONG_TESTS=1.
 """
 import os
 
@@ -114,47 +115,39 @@ def test_c3_chunk_measures_match_oracle(c3):
 
 
 @pytest.mark.skipif(os.environ.get("GF_LONG_TESTS") != "1",
-                    reason="the 64^3 x 256 fix runs 100k sweeps (about 9 minutes); set GF_LONG_TESTS=1")
+                    reason="the complete 64^3 x 256 fix runs about 150k sweeps (about 13 minutes); "
+                           "set GF_LONG_TESTS=1")
 def test_c3_full_fix(c3):
     # The time-slices converge at very different rates (the slowest gauge
     # modes of a 64^3 slice decay by about 1 - c omega lambda_min per sweep,
     # and lambda_min varies between slices): most stop between 30k and 100k
-    # sweeps, a few need longer.  The test runs 100k sweeps and checks every
-    # stopped slice, and that the slices still running are close and keep
-    # stopping.
+    # sweeps, the last few need up to about 150k (one run: 31,080 to 150,020
+    # sweeps, quartiles 45.8k / 56.2k / 68.8k).  Once most slices have
+    # stopped a sweep costs well under a millisecond, so the test runs until
+    # every slice has stopped, within 300k sweeps, in calls of 10k sweeps
+    # (checks every 20; a converged time-slice stops at the first check of
+    # the next call, and each call ends with the U_0 fix-up, so the calls
+    # continue one run).
     fx, buf = c3
     say("C3: full fix")
     _upload(fx, buf)
-    # in calls of 2000 sweeps (a converged time-slice stops at the first
-    # check of the next call, and each call ends with the U_0 fix-up, so the
-    # chunks continue one run)
     done = np.zeros(DIMS[0], dtype=np.int64)
-    hist = []
-    for chunk in range(50):
-        st, d = fx.sweep("or", max_sweeps=2000, tol=1e-12, check_every=10)
+    st = 1
+    for chunk in range(30):
+        st, d = fx.sweep("or", max_sweeps=10000, tol=1e-12, check_every=20)
         done += d
-        running = d == 2000
+        running = d == 10000
         _, th = fx.measure_timeslices(0)
-        hist.append(th)
         say("  after", int(done.max()), "sweeps: status", st, "slices still running", int(np.sum(running)),
             "their theta max", float(th[running].max()) if running.any() else 0.0)
         if st == 0:
             break
-    stopped = ~running if st != 0 else np.ones(DIMS[0], bool)
-    Ft0, tht0 = fx.measure_timeslices(0)
-    say("status", st, "slices stopped", int(stopped.sum()), "sweeps min/max", done.min(), done.max(),
-        "theta max of stopped slices", tht0[stopped].max())
-    assert stopped.sum() >= 0.9 * DIMS[0]
-    assert np.all(tht0[stopped] < 1e-12)
-    assert len(set(done[stopped].tolist())) > 1  # time-slices stop on their own
-    if st != 0:
-        # the slices still running are close (theta is not monotonic under
-        # overrelaxation, so no per-slice trend is asserted) and slices keep
-        # stopping: fewer run now than 20k sweeps ago
-        assert np.all(hist[-1][~stopped] < 1e-6)
-        assert np.sum(~stopped) < np.sum(hist[-11] >= 1e-12)
     Ft, tht = fx.measure_timeslices(0)
-    assert np.all(tht[stopped] < 1e-12)
+    say("status", st, "sweeps min/max", done.min(), done.max(), "quartiles", np.percentile(done, [25, 50, 75]),
+        "theta_t max", tht.max())
+    assert st == 0  # every time-slice stopped
+    assert np.all(tht < 1e-12)
+    assert len(set(done.tolist())) > 1  # time-slices stop on their own
     d1 = (1,) + DIMS[1:]
     for t in SLICES:
         got = fx.download(0, t0=t, nt=1)
