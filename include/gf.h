@@ -196,7 +196,10 @@ int gf_set_anneal(gf_handle h, double T0, double T1, int32_t nsteps, int32_t nmi
    reprojected and satisfy theta < theta_tol.
    Coulomb: the U_0 fix-up follows at the end.  Stopped units are neither
    swept nor reprojected by the periodic reprojection: a unit keeps the
-   links its stopping check measured.
+   links its stopping check measured.  Later checks read only the units
+   still running (a stopped unit's F and theta stay those of its stopping
+   check), and with cache groups (gf_set_cache_budget) a group whose units
+   have all stopped is no longer launched.
    GF_ANNEAL: run the schedule of gf_set_anneal (no stopping; max_sweeps,
    theta_tol, check_every ignored).
    sweeps_done (host, may be NULL): per instance (Landau/MAG) or per

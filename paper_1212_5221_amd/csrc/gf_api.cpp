@@ -47,6 +47,7 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     int key_upd = -1, key_n = -1, key_W = -1, key_tail = -1, key_r = -1;
+    std::vector<uint8_t> key_live;  // the groups the chunk sweeps (empty: all)
 };
 
 struct GraphCache {
@@ -105,6 +106,7 @@ struct gf_ctx {
     // host readback (pinned)
     int32_t *hstat = nullptr;
     double *hres = nullptr;
+    int32_t *hact = nullptr;  // per-unit active flags of the two check slots (with cache groups)
 
     // timing: inside gf_sweep every time_every-th chunk runs plain launches,
     // each bracketed by events (time_now), the others replay graphs;
@@ -130,6 +132,11 @@ struct gf_ctx {
     // every unit's sequence of sweeps is unchanged)
     int64_t cache_budget = (int64_t)224 << 20;
     std::vector<int> grp_u0;         // group g = units [grp_u0[g], grp_u0[g + 1])
+    // inside gf_sweep, with several groups: 1 for each group that had an
+    // active unit at the last check read (empty: sweep every group).  Units
+    // only stop there, so a group whose units have all stopped is skipped:
+    // its kernels would exit at once, but their launches still cost time.
+    std::vector<uint8_t> grp_live;
     std::vector<int32_t> tile_u0[3]; // per tile table: first tile of each unit (+ end)
 
     // from the last check: active units, of which in the FP64 tail
@@ -586,13 +593,25 @@ int launch_sweep(gf_ctx *h, int upd, double T, bool reunit_now, bool capturing, 
 int enqueue_chunk(gf_ctx *h, int upd, int n, int k0, bool capturing) {
     const int R = h->reunit_every;
     const int ng = ngroups(h);
-    for (int g = 0; g < ng; ++g)
+    for (int g = 0; g < ng; ++g) {
+        if (ng > 1 && !h->grp_live.empty() && !h->grp_live[g]) continue;  // every unit has stopped
         for (int i = 0; i < n; ++i) {
             const bool rn = (R > 0) && ((k0 + i + 1) % R == 0);
             int rc = launch_sweep(h, upd, h->T, rn, capturing, i, ng > 1 ? g : -1);
             if (rc) return rc;
         }
+    }
     return GF_OK;
+}
+
+// groups with an active unit, from per-unit active flags
+void set_live_groups(gf_ctx *h, const int32_t *active) {
+    const int ng = ngroups(h);
+    for (int g = 0; g < ng; ++g) {
+        uint8_t live = 0;
+        for (int u = h->grp_u0[g]; u < h->grp_u0[g + 1] && !live; ++u) live = active[u] != 0;
+        h->grp_live[g] = live;
+    }
 }
 
 // after a chunk of n sweeps: sweeps_done and the random-stream index
@@ -603,8 +622,10 @@ int count_chunk(gf_ctx *h, int n) {
 }
 
 // F / theta of every unit; with decide, also the stopping decision (one
-// finalize kernel whose last block decides)
-int launch_measure(gf_ctx *h, int with_unitarity, bool decide = false, double tol = 0.0) {
+// finalize kernel whose last block decides).  only_active (inside gf_sweep):
+// the tiles of stopped units are not read again, their partial sums from
+// the measurement that stopped them stand (their links have not changed)
+int launch_measure(gf_ctx *h, int with_unitarity, bool decide = false, double tol = 0.0, bool only_active = false) {
     gfs::MeasureArgs a;
     a.ws = h->ws;
     a.inst = wsp<gfs::InstDev>(h, h->off_inst);
@@ -612,7 +633,8 @@ int launch_measure(gf_ctx *h, int with_unitarity, bool decide = false, double to
     a.tiles = wsp<gfs::MTile>(h, h->off_mtiles);
     a.partial = wsp<double>(h, h->off_partial);
     a.with_unitarity = with_unitarity;
-    HIPCHK(h, gfl::measure(h->gauge, st_code(h), (unsigned)h->nmtiles, h->cur, a));
+    HIPCHK(h, gfl::measure(h->gauge, st_code(h), (unsigned)h->nmtiles, h->cur, a,
+                           only_active ? wsp<int32_t>(h, h->off_active) : nullptr));
     if (!decide) {
         HIPCHK(h, gfl::finalize(h->nunits, wsp<gfs::UnitDev>(h, h->off_unit), wsp<double>(h, h->off_partial),
                                 ndir(h), h->nc, wsp<double>(h, h->off_res), h->cur));
@@ -671,7 +693,9 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
     GraphCache &gc = h->graph;
     GraphEntry *g = nullptr;
     for (auto &x : gc.e)
-        if (x.key_upd == upd && x.key_n == n && x.key_W == wkey && x.key_tail == tailkey && x.key_r == rkey) g = &x;
+        if (x.key_upd == upd && x.key_n == n && x.key_W == wkey && x.key_tail == tailkey && x.key_r == rkey &&
+            x.key_live == h->grp_live)
+            g = &x;
     if (!g) {
         if (gc.e.size() >= GraphCache::kMax) gc.clear();
         if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
@@ -699,6 +723,7 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
         ne.key_W = wkey;
         ne.key_tail = tailkey;
         ne.key_r = rkey;
+        ne.key_live = h->grp_live;
         gc.e.push_back(ne);
         g = &gc.e.back();
     }
@@ -777,6 +802,7 @@ void gf_destroy(gf_handle h) {
     for (auto e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->hstat) (void)hipHostFree(h->hstat);
     if (h->hres) (void)hipHostFree(h->hres);
+    if (h->hact) (void)hipHostFree(h->hact);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     for (auto e : h->chk_ev)
         if (e) (void)hipEventDestroy(e);
@@ -1024,7 +1050,9 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
     if (upd < 0) return fail(h, GF_E_INVALID, "bad update type %d", update);
     if (max_sweeps < 0) return fail(h, GF_E_INVALID, "max_sweeps < 0");
     if (check_every < 1) check_every = 1;
-    // Checks at k = 0, c, 2c, ... measure theta and stop units on the device.
+    // Checks at k = 0, c, 2c, ... measure theta and stop units on the device
+    // (a check reads only the units still active; a stopped unit's partial
+    // sums from its stopping check stand, since its links do not change).
     // The next chunk of sweeps is enqueued before the host reads a check's
     // status: sweep kernels skip stopped units, so a chunk queued after the
     // last unit stopped changes nothing, and the GPU never idles while the
@@ -1032,16 +1060,32 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
     // the check before, which keeps the schedule deterministic.
     for (int e = 0; e < 2; ++e)
         if (!h->chk_ev[e]) HIPCHK(h, hipEventCreateWithFlags(&h->chk_ev[e], hipEventDisableTiming));
+    // with cache groups, each check also reads the per-unit active flags,
+    // and groups whose units have all stopped are skipped from then on
+    const int ng = ngroups(h);
+    struct LiveGuard {
+        gf_ctx *h;
+        ~LiveGuard() { h->grp_live.clear(); }
+    } live_guard{h};
+    if (ng > 1) {
+        if (!h->hact)
+            HIPCHK(h, hipHostMalloc(reinterpret_cast<void **>(&h->hact), 2 * sizeof(int32_t) * h->nunits,
+                                    hipHostMallocDefault));
+        h->grp_live.assign(ng, 1);
+    }
     struct Pend {
         int slot, k;
     };
     Pend pend[2];
     int npend = 0, slot = 0;
     auto enqueue_check = [&](int kk) -> int {
-        int r = launch_measure(h, 0, true, theta_tol);
+        int r = launch_measure(h, 0, true, theta_tol, true);
         if (r) return r;
         HIPCHK(h, hipMemcpyAsync(h->hstat + 4 * slot, h->ws + h->off_status, 3 * sizeof(int32_t),
                                  hipMemcpyDeviceToHost, h->stream));
+        if (ng > 1)
+            HIPCHK(h, hipMemcpyAsync(h->hact + (size_t)slot * h->nunits, h->ws + h->off_active,
+                                     sizeof(int32_t) * h->nunits, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(h, hipEventRecord(h->chk_ev[slot], h->stream));
         pend[npend++] = {slot, kk};
         slot ^= 1;
@@ -1070,6 +1114,7 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
                     stopped = true;
                     return GF_OK;
                 }
+                if (ng > 1) set_live_groups(h, h->hact + (size_t)c.slot * h->nunits);
                 continue;
             }
             if (k >= max_sweeps) return GF_OK;
@@ -1112,7 +1157,7 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
             }
             HIPCHK(h, hipMemcpyAsync(h->ws + h->off_active, ran.data(), sizeof(int32_t) * h->nunits,
                                      hipMemcpyHostToDevice, h->stream));
-            rc = launch_measure(h, 0, true, theta_tol);
+            rc = launch_measure(h, 0, true, theta_tol, true);
             if (rc) return rc;
             HIPCHK(h, hipMemcpyAsync(h->hstat, h->ws + h->off_status, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
                                      h->stream));
@@ -1126,6 +1171,7 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
             h->n_active = h->hstat[0];
             h->n_tail = h->hstat[2];
             if (h->n_active == 0) break;
+            if (ng > 1) set_live_groups(h, ran.data());
             if (k >= max_sweeps) {
                 stopped = false;
                 break;

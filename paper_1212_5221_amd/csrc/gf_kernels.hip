@@ -52,7 +52,7 @@ __device__ __forceinline__ cx<double> det3(const M3<double> &m) {
 // brought into L2, and only the t-direction ones come from further away.
 // Partials per tile.
 template <int GAUGE, int ST>
-__global__ __launch_bounds__(MBLOCK) void k_measure(gfs::MeasureArgs a) {
+__global__ __launch_bounds__(MBLOCK) void k_measure(gfs::MeasureArgs a, const int32_t *active) {
     typedef Store<ST> SD;
     constexpr int NDIR = (GAUGE == gfs::COULOMB) ? 3 : 4;
     constexpr int MU0 = (GAUGE == gfs::COULOMB) ? 1 : 0;
@@ -60,6 +60,9 @@ __global__ __launch_bounds__(MBLOCK) void k_measure(gfs::MeasureArgs a) {
     __shared__ double sh[4];
     const int tix = xcd_tile(blockIdx.x, gridDim.x);
     const gfs::MTile tl = a.tiles[tix];
+    // a stopped unit's links have not changed since its last measurement
+    // (the whole block belongs to one unit, so it returns as a whole)
+    if (active && !active[tl.unit]) return;
     const gfs::UnitDev U = a.unit[tl.unit];
     const gfs::InstDev I = a.inst[U.inst];
     int32_t j = tl.j0 + (int32_t)(threadIdx.x % gfs::MTILE_SITES);
@@ -473,22 +476,24 @@ using namespace gfd;
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + MBLOCK - 1) / MBLOCK); }
 
 template <int G>
-static hipError_t measure_g(int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a) {
+static hipError_t measure_g(int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a,
+                            const int32_t *active) {
     if (st == gfs::ST_F64R18)
-        k_measure<G, gfs::ST_F64R18><<<ntiles, MBLOCK, 0, s>>>(a);
+        k_measure<G, gfs::ST_F64R18><<<ntiles, MBLOCK, 0, s>>>(a, active);
     else if (st == gfs::ST_F64R12)
-        k_measure<G, gfs::ST_F64R12><<<ntiles, MBLOCK, 0, s>>>(a);
+        k_measure<G, gfs::ST_F64R12><<<ntiles, MBLOCK, 0, s>>>(a, active);
     else
-        k_measure<G, gfs::ST_F32R12><<<ntiles, MBLOCK, 0, s>>>(a);
+        k_measure<G, gfs::ST_F32R12><<<ntiles, MBLOCK, 0, s>>>(a, active);
     return hipGetLastError();
 }
 
-hipError_t measure(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a) {
+hipError_t measure(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a,
+                   const int32_t *active) {
     if (ntiles == 0) return hipSuccess;
-    if (gfs::is_su2(st)) return measure_su2(gauge, st, ntiles, s, a);
-    if (gauge == gfs::LANDAU) return measure_g<gfs::LANDAU>(st, ntiles, s, a);
-    if (gauge == gfs::COULOMB) return measure_g<gfs::COULOMB>(st, ntiles, s, a);
-    return measure_g<gfs::MAG>(st, ntiles, s, a);
+    if (gfs::is_su2(st)) return measure_su2(gauge, st, ntiles, s, a, active);
+    if (gauge == gfs::LANDAU) return measure_g<gfs::LANDAU>(st, ntiles, s, a, active);
+    if (gauge == gfs::COULOMB) return measure_g<gfs::COULOMB>(st, ntiles, s, a, active);
+    return measure_g<gfs::MAG>(st, ntiles, s, a, active);
 }
 
 hipError_t finalize(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, int nc, double *out,

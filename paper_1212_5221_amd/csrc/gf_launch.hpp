@@ -21,7 +21,10 @@ sweep_fn su3_lookup(int upd, int ctd, int wi, int bi, int nt);
 // gauge group SU(2) (storages ST_SU2_*; W = 1, nt = 0)
 sweep_fn sweep_kernel_su2(int gauge, int upd, int st, int ct_double, int W, int B, int nt);
 
-hipError_t measure(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a);
+// active != nullptr: the tiles of units whose flag is 0 are skipped and keep
+// their partial sums from the last measurement
+hipError_t measure(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a,
+                   const int32_t *active = nullptr);
 // unit sums -> F = sum / (nc ndir V_u), theta = sum / (nc V_u) (nc: 3 or 2)
 hipError_t finalize(int nunits, const gfs::UnitDev *units, const double *partial, int ndir, int nc, double *out,
                     hipStream_t s);
@@ -44,7 +47,8 @@ hipError_t convert_out(int st, const char *ws, const gfs::InstDev &I, double *ds
 hipError_t coulomb_fix(int st, char *ws, const gfs::InstDev &I, hipStream_t s);
 
 // the same for the SU(2) storages (the functions above dispatch to these)
-hipError_t measure_su2(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a);
+hipError_t measure_su2(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a,
+                       const int32_t *active);
 hipError_t reunit_su2(int st, char *ws, int64_t off, int32_t nplanes, int32_t Vp, int32_t h_lo, int32_t nh,
                       const int32_t *active, int32_t unit0, int32_t hper, hipStream_t s);
 hipError_t set_identity_su2(int st, char *ws, int64_t off, int32_t Vh, int32_t Vp, hipStream_t s);

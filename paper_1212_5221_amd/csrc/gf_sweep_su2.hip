@@ -214,7 +214,7 @@ __device__ __forceinline__ void ck_matrix(const Q4<double> &u, cx<double> m[2][2
 // d = sum_mu u_vec(x) - u_vec(x - mu), so 2 |d|^2; MAG |X_01|^2 with
 // X = sum_mu U sigma_3 U^dag + U'^dag sigma_3 U', Sec. 2.1.2), and |1 - det U|.
 template <int GAUGE, int ST>
-__global__ __launch_bounds__(MBLOCK) void k_measure_su2(gfs::MeasureArgs a) {
+__global__ __launch_bounds__(MBLOCK) void k_measure_su2(gfs::MeasureArgs a, const int32_t *active) {
     typedef Store<ST> SD;
     constexpr int NDIR = (GAUGE == gfs::COULOMB) ? 3 : 4;
     constexpr int MU0 = (GAUGE == gfs::COULOMB) ? 1 : 0;
@@ -222,6 +222,7 @@ __global__ __launch_bounds__(MBLOCK) void k_measure_su2(gfs::MeasureArgs a) {
     __shared__ double sh[4];
     const int tix = xcd_tile(blockIdx.x, gridDim.x);
     const gfs::MTile tl = a.tiles[tix];
+    if (active && !active[tl.unit]) return;  // a stopped unit keeps its partial sums
     const gfs::UnitDev U = a.unit[tl.unit];
     const gfs::InstDev I = a.inst[U.inst];
     int32_t j = tl.j0 + (int32_t)(threadIdx.x % gfs::MTILE_SITES);
@@ -453,21 +454,22 @@ sweep_fn sweep_kernel_su2(int gauge, int upd, int st, int ctd, int W, int B, int
 static inline unsigned nblk_su2(int64_t n) { return (unsigned)((n + MBLOCK - 1) / MBLOCK); }
 
 template <int G>
-static void measure_su2_g(int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a) {
+static void measure_su2_g(int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a, const int32_t *active) {
     if (st == gfs::ST_SU2_F64)
-        k_measure_su2<G, gfs::ST_SU2_F64><<<ntiles, MBLOCK, 0, s>>>(a);
+        k_measure_su2<G, gfs::ST_SU2_F64><<<ntiles, MBLOCK, 0, s>>>(a, active);
     else
-        k_measure_su2<G, gfs::ST_SU2_F32><<<ntiles, MBLOCK, 0, s>>>(a);
+        k_measure_su2<G, gfs::ST_SU2_F32><<<ntiles, MBLOCK, 0, s>>>(a, active);
 }
 
-hipError_t measure_su2(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a) {
+hipError_t measure_su2(int gauge, int st, unsigned ntiles, hipStream_t s, const gfs::MeasureArgs &a,
+                       const int32_t *active) {
     if (ntiles == 0) return hipSuccess;
     if (gauge == gfs::LANDAU)
-        measure_su2_g<gfs::LANDAU>(st, ntiles, s, a);
+        measure_su2_g<gfs::LANDAU>(st, ntiles, s, a, active);
     else if (gauge == gfs::COULOMB)
-        measure_su2_g<gfs::COULOMB>(st, ntiles, s, a);
+        measure_su2_g<gfs::COULOMB>(st, ntiles, s, a, active);
     else
-        measure_su2_g<gfs::MAG>(st, ntiles, s, a);
+        measure_su2_g<gfs::MAG>(st, ntiles, s, a, active);
     return hipGetLastError();
 }
 
