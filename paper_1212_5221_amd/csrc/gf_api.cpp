@@ -575,7 +575,6 @@ int launch_reunit_units(gf_ctx *h, bool only_active, int u0, int u1) {
 
 int launch_reunit_all(gf_ctx *h, bool only_active) { return launch_reunit_units(h, only_active, 0, h->nunits); }
 
-// one full sweep (both parities) + bookkeeping [+ reprojection]
 // one full sweep (both parities) [+ reprojection]; sweep_off is the sweep's
 // position in its chunk (random counter offset), counted by count_chunk
 int launch_sweep(gf_ctx *h, int upd, double T, bool reunit_now, bool capturing, int sweep_off, int grp = -1) {
