@@ -727,6 +727,9 @@ def main():
     ap.add_argument("--profile-heatbath", type=int, default=0,
                     help="only run this many heatbath sweeps (T = 0.5) of the 32^4 workload in Landau and MAG gauge, "
                          "mixed storage (for profiler counter runs)")
+    ap.add_argument("--profile-coulomb", type=int, default=0,
+                    help="only run this many OR sweeps of the 64^3 x 256 Coulomb configuration (mixed storage, "
+                         "Infinity-Cache groups, after autotuning and a warm-up; for profiler runs)")
     ap.add_argument("--profile-su2", type=int, default=0,
                     help="only run this many OR sweeps of the 32^4 SU(2) Landau field, mixed storage "
                          "(for profiler counter runs)")
@@ -784,6 +787,31 @@ def main():
             out[gauge] = {"launches": n, "mean_launch_ms": ms, "shape": fx.get_shape("heatbath")}
             fx.close()
         print(json.dumps(out), flush=True)
+        return
+    if args.profile_coulomb:
+        # 64^3 x 256 Coulomb, 16 generated time-slices repeated 16 times (as in
+        # the workload's throughput line), default cache budget: the sweeps run
+        # group by group; tol 0, so every time-slice runs every sweep
+        dims = (256, 64, 64, 64)
+        slab = torch.from_numpy(I.smooth(dims, 0.5, 3001, t0=0, nt=16).reshape(-1)).to("cuda:0")
+        fx = gf.GaugeFixer([dims], gauge="coulomb", storage="mixed", reunit_every=100, tail_theta=1e-9)
+        for t0 in range(0, 256, 16):
+            fx.upload(0, slab, t0=t0, nt=16)
+        del slab
+        fx.set_overrelax(OMEGA)
+        fx.autotune(reps=2)
+        warm_up(fx, "or")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fx.sweep("or", max_sweeps=args.profile_coulomb, tol=0.0, check_every=CHECK)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        groups = fx.cache_groups()
+        shape = fx.get_shape("fp32")
+        fx.close()
+        print(json.dumps({"profile_coulomb_sweeps": args.profile_coulomb, "lattice": list(dims), "cache_groups": groups,
+                          "shape": "%d/%d/%d" % shape, "ms_per_sweep": el / args.profile_coulomb * 1e3,
+                          "bytes_per_site_update": 672}), flush=True)
         return
     if args.profile_su2:
         # 32^4 SU(2), eps 0.5, seed 2001: one upload, then the sweeps in one
