@@ -132,10 +132,12 @@ struct gf_ctx {
     // every unit's sequence of sweeps is unchanged)
     int64_t cache_budget = (int64_t)224 << 20;
     std::vector<int> grp_u0;         // group g = units [grp_u0[g], grp_u0[g + 1])
-    // inside gf_sweep, with several groups: 1 for each group that had an
-    // active unit at the last check read (empty: sweep every group).  Units
-    // only stop there, so a group whose units have all stopped is skipped:
-    // its kernels would exit at once, but their launches still cost time.
+    // inside gf_sweep, per group, from the last check read: 0 every unit
+    // stopped, 1 some stopped, 2 all active (empty: outside gf_sweep, sweep
+    // every group as all active).  Units only stop at checks, so a group
+    // whose units have all stopped is skipped (its kernels would exit at
+    // once, but their launches still cost time), and a group with stopped
+    // units is launched in the linear tile order (see launch_half).
     std::vector<uint8_t> grp_live;
     std::vector<int32_t> tile_u0[3]; // per tile table: first tile of each unit (+ end)
 
@@ -531,7 +533,14 @@ int launch_half(gf_ctx *h, int upd, int parity, double T, bool capturing, int sw
                         upd, h->storage, sh.W, sh.B);
         int nt = 0;
         gfs::SweepArgs a = sweep_args(h, parity, launches[k].sel, T, tab, sweep_off, grp, &nt);
-        a.xcd_order = sh.xcd;
+        // The XCD-contiguous order hands each XCD a contiguous eighth of the
+        // tiles.  When only some units of the launch do work (stopped units,
+        // or the units of the other precision, whose blocks exit at once),
+        // the working tiles would crowd onto a few XCDs; the linear order
+        // deals consecutive blocks round the XCDs and spreads them.
+        const bool uniform =
+            launches[k].sel < 0 && (h->grp_live.empty() || h->grp_live[grp < 0 ? 0 : grp] == 2);
+        a.xcd_order = sh.xcd && uniform;
         if (nt <= 0) continue;
         const bool tm = h->timing && !capturing && h->time_now;
         if (tm) {
@@ -593,7 +602,7 @@ int enqueue_chunk(gf_ctx *h, int upd, int n, int k0, bool capturing) {
     const int R = h->reunit_every;
     const int ng = ngroups(h);
     for (int g = 0; g < ng; ++g) {
-        if (ng > 1 && !h->grp_live.empty() && !h->grp_live[g]) continue;  // every unit has stopped
+        if (ng > 1 && !h->grp_live.empty() && h->grp_live[g] == 0) continue;  // every unit has stopped
         for (int i = 0; i < n; ++i) {
             const bool rn = (R > 0) && ((k0 + i + 1) % R == 0);
             int rc = launch_sweep(h, upd, h->T, rn, capturing, i, ng > 1 ? g : -1);
@@ -603,13 +612,13 @@ int enqueue_chunk(gf_ctx *h, int upd, int n, int k0, bool capturing) {
     return GF_OK;
 }
 
-// groups with an active unit, from per-unit active flags
+// per group: 0 no active unit, 1 some, 2 all, from per-unit active flags
 void set_live_groups(gf_ctx *h, const int32_t *active) {
     const int ng = ngroups(h);
     for (int g = 0; g < ng; ++g) {
-        uint8_t live = 0;
-        for (int u = h->grp_u0[g]; u < h->grp_u0[g + 1] && !live; ++u) live = active[u] != 0;
-        h->grp_live[g] = live;
+        int n = 0;
+        for (int u = h->grp_u0[g]; u < h->grp_u0[g + 1]; ++u) n += active[u] != 0;
+        h->grp_live[g] = (n == 0) ? 0 : (n == h->grp_u0[g + 1] - h->grp_u0[g] ? 2 : 1);
     }
 }
 
@@ -1059,19 +1068,18 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
     // the check before, which keeps the schedule deterministic.
     for (int e = 0; e < 2; ++e)
         if (!h->chk_ev[e]) HIPCHK(h, hipEventCreateWithFlags(&h->chk_ev[e], hipEventDisableTiming));
-    // with cache groups, each check also reads the per-unit active flags,
-    // and groups whose units have all stopped are skipped from then on
+    // each check also reads the per-unit active flags: groups whose units
+    // have all stopped are skipped from then on, and groups with some
+    // stopped units are launched in the linear tile order
     const int ng = ngroups(h);
     struct LiveGuard {
         gf_ctx *h;
         ~LiveGuard() { h->grp_live.clear(); }
     } live_guard{h};
-    if (ng > 1) {
-        if (!h->hact)
-            HIPCHK(h, hipHostMalloc(reinterpret_cast<void **>(&h->hact), 2 * sizeof(int32_t) * h->nunits,
-                                    hipHostMallocDefault));
-        h->grp_live.assign(ng, 1);
-    }
+    if (!h->hact)
+        HIPCHK(h, hipHostMalloc(reinterpret_cast<void **>(&h->hact), 2 * sizeof(int32_t) * h->nunits,
+                                hipHostMallocDefault));
+    h->grp_live.assign(ng, 2);
     struct Pend {
         int slot, k;
     };
@@ -1082,9 +1090,8 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
         if (r) return r;
         HIPCHK(h, hipMemcpyAsync(h->hstat + 4 * slot, h->ws + h->off_status, 3 * sizeof(int32_t),
                                  hipMemcpyDeviceToHost, h->stream));
-        if (ng > 1)
-            HIPCHK(h, hipMemcpyAsync(h->hact + (size_t)slot * h->nunits, h->ws + h->off_active,
-                                     sizeof(int32_t) * h->nunits, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->hact + (size_t)slot * h->nunits, h->ws + h->off_active,
+                                 sizeof(int32_t) * h->nunits, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(h, hipEventRecord(h->chk_ev[slot], h->stream));
         pend[npend++] = {slot, kk};
         slot ^= 1;
@@ -1113,7 +1120,7 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
                     stopped = true;
                     return GF_OK;
                 }
-                if (ng > 1) set_live_groups(h, h->hact + (size_t)c.slot * h->nunits);
+                set_live_groups(h, h->hact + (size_t)c.slot * h->nunits);
                 continue;
             }
             if (k >= max_sweeps) return GF_OK;
@@ -1170,7 +1177,7 @@ int gf_sweep(gf_handle h, int update, int32_t max_sweeps, double theta_tol, int3
             h->n_active = h->hstat[0];
             h->n_tail = h->hstat[2];
             if (h->n_active == 0) break;
-            if (ng > 1) set_live_groups(h, ran.data());
+            set_live_groups(h, ran.data());
             if (k >= max_sweeps) {
                 stopped = false;
                 break;
