@@ -198,8 +198,10 @@ int gf_set_anneal(gf_handle h, double T0, double T1, int32_t nsteps, int32_t nmi
    swept nor reprojected by the periodic reprojection: a unit keeps the
    links its stopping check measured.  Later checks read only the units
    still running (a stopped unit's F and theta stay those of its stopping
-   check), and with cache groups (gf_set_cache_budget) a group whose units
-   have all stopped is no longer launched.
+   check), with cache groups (gf_set_cache_budget) a group whose units
+   have all stopped is no longer launched, and a launch in which only some
+   units work runs in the linear tile order (the working tiles spread over
+   all XCDs) whatever the shape's tile order.
    GF_ANNEAL: run the schedule of gf_set_anneal (no stopping; max_sweeps,
    theta_tol, check_every ignored).
    sweeps_done (host, may be NULL): per instance (Landau/MAG) or per
@@ -271,7 +273,9 @@ int gf_set_sweep_index(gf_handle h, int32_t inst, uint64_t index);
    - flags: GF_SHAPE_NONTEMPORAL loads and stores the links with the
      non-temporal (streaming) cache policy (overrelaxation and
      microcanonical kernels; SU(3) only), GF_SHAPE_LINEAR_TILES hands tile b
-     to block b instead of giving every XCD a contiguous range of tiles.
+     to block b instead of giving every XCD a contiguous range of tiles
+     (inside gf_sweep a launch in which only some units work always uses
+     the linear order).
    The default is waves_per_site 1 for the FP32 update, 4 (or the largest
    available) for the FP64 update, for the heatbath 1 on FP32 storage, 2 on
    FP64-12, 4 on FP64-18; block 256; no flags.  Results do not depend on the

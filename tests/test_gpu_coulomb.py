@@ -7,7 +7,7 @@ site by site by the oracle from the same FP32-rounded input slice (the
 update of a time-slice depends on that slice only), and after the full fix
 the oracle's per-slice F_t and theta_t of the downloaded slice, after a
 bounded chunk of 2000 sweeps of all slices.  The complete fix (every
-time-slice below 1e-12, about 150k sweeps and 13 minutes) runs only with
+time-slice below 1e-12, about 150k sweeps and 9 minutes) runs only with
 GF_LONG_TESTS=1.
 """
 import os
@@ -115,7 +115,7 @@ def test_c3_chunk_measures_match_oracle(c3):
 
 
 @pytest.mark.skipif(os.environ.get("GF_LONG_TESTS") != "1",
-                    reason="the complete 64^3 x 256 fix runs about 150k sweeps (about 13 minutes); "
+                    reason="the complete 64^3 x 256 fix runs about 150k sweeps (about 9 minutes); "
                            "set GF_LONG_TESTS=1")
 def test_c3_full_fix(c3):
     # The time-slices converge at very different rates (the slowest gauge
