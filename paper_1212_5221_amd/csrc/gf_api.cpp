@@ -50,15 +50,24 @@ struct GraphEntry {
     std::vector<uint8_t> key_live;  // the groups the chunk sweeps (empty: all)
 };
 
+// the captured chunks, least recently used first; when full, the least
+// recently used one is dropped (a batch whose units stop one by one needs a
+// new graph per set of live groups, while the few reprojection positions
+// of the current set keep being replayed)
 struct GraphCache {
-    static constexpr size_t kMax = 16;
+    static constexpr size_t kMax = 32;
     std::vector<GraphEntry> e;
+    static void destroy(GraphEntry &g) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
     void clear() {
-        for (auto &g : e) {
-            if (g.exec) (void)hipGraphExecDestroy(g.exec);
-            if (g.graph) (void)hipGraphDestroy(g.graph);
-        }
+        for (auto &g : e) destroy(g);
         e.clear();
+    }
+    void drop_oldest() {
+        destroy(e.front());
+        e.erase(e.begin());
     }
 };
 
@@ -700,12 +709,17 @@ int run_sweeps(gf_ctx *h, int upd, int n, int k0, bool chunk_is_full) {
     }
     GraphCache &gc = h->graph;
     GraphEntry *g = nullptr;
-    for (auto &x : gc.e)
+    for (size_t i = 0; i < gc.e.size(); ++i) {
+        const GraphEntry &x = gc.e[i];
         if (x.key_upd == upd && x.key_n == n && x.key_W == wkey && x.key_tail == tailkey && x.key_r == rkey &&
-            x.key_live == h->grp_live)
-            g = &x;
+            x.key_live == h->grp_live) {
+            std::rotate(gc.e.begin() + i, gc.e.begin() + i + 1, gc.e.end());  // now the most recent
+            g = &gc.e.back();
+            break;
+        }
+    }
     if (!g) {
-        if (gc.e.size() >= GraphCache::kMax) gc.clear();
+        if (gc.e.size() >= GraphCache::kMax) gc.drop_oldest();
         if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
         HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
         h->cur = h->cap;
