@@ -1,5 +1,6 @@
-"""bench.py host logic (no GPU): the one-GPU guard and the rule that measured
-HBM bytes are reported only for the kernel sources they were taken from."""
+"""bench.py host logic (no GPU): the one-GPU guard, the rule that measured
+HBM bytes are reported only for the kernel sources they were taken from, and
+that the profile summaries name those same sources."""
 import os
 import subprocess
 import sys
@@ -26,3 +27,18 @@ def test_traffic_only_for_the_profiled_kernel_sources(monkeypatch):
     assert bench.measured_traffic("1/256/0") is None
     monkeypatch.setattr(bench, "COUNTER_DIGEST", None)
     assert bench.measured_traffic("1/256/0") is None
+
+
+def test_profiles_name_the_digest_the_counters_hold():
+    # every profile summary that states the kernel sources it was taken
+    # from states the digest under which bench.py reports the counted bytes
+    import re
+    import bench
+    pdir = os.path.join(ROOT, "profiles")
+    found = {}
+    for name in sorted(os.listdir(pdir)):
+        text = open(os.path.join(pdir, name)).read()
+        for d in re.findall(r"digest\s+([0-9a-f]{16})", text):
+            found.setdefault(d, []).append(name)
+    assert found, "no profile states its kernel sources digest"
+    assert set(found) == {bench.COUNTER_DIGEST}, found
