@@ -142,8 +142,9 @@ STREAM_KINDS = {"copy": 0, "copy_nt_load": 1, "copy_nt_store": 2, "copy_nt": 3, 
 
 
 def stream(kind, dst, src, nbytes, stream=None):
-    """gf_stream: one streaming pass (copy or read) over nbytes of CUDA
-    tensors, enqueued on `stream` (default: torch's current stream)."""
+    """gf_stream: one streaming pass (copy, or read) over nbytes of CUDA
+    tensors, enqueued on `stream` (default: torch's current stream); a copy
+    with dst the same tensor as src is an in-place pass."""
     import torch
     L = load()
     if stream is None:
